@@ -1,0 +1,124 @@
+"""Seeded synthetic initial fields for the workloads (host side, numpy FP64).
+
+This module builds input data only. It holds none of the method's arithmetic
+(no sampling noise, no evolution, no moments); both the GPU path and the CPU
+oracle are fed from it. Every field is returned as a complex128 array in
+numpy order (x fastest, shape (n2, n1, n0) / (n1, n0) / (n0,)) normalised to
+sum_g |psi|^2 dV = 1, the normalisation of the paper's psi'.
+"""
+import numpy as np
+
+
+def _grid_coords(n, box):
+    """Cell-corner coordinates x_g = g dx per axis, broadcast in numpy order."""
+    dim = len(n)
+    out = []
+    for d in range(dim):
+        x = np.arange(n[d]) * (box[d] / n[d])
+        shape = [1] * dim
+        shape[dim - 1 - d] = n[d]
+        out.append(x.reshape(shape))
+    return out
+
+
+def normalise(psi, n, box):
+    dv = float(np.prod([box[d] / n[d] for d in range(len(n))]))
+    return psi / np.sqrt((np.abs(psi) ** 2).sum() * dv)
+
+
+def lognormal_field(n, box, kcut=None, amp=0.5, seed=0):
+    """sqrt of a positive Gaussian-random density with spectrum P(k) ~ k^-2.
+
+    delta_j = (a + i b)/|j| for 1 <= |j| <= kcut (integer wavevector j,
+    a, b ~ N(0,1) from numpy default_rng(seed)), delta = Re IDFT, scaled to unit
+    rms; rho ~ exp(amp*delta - amp^2/2); psi = sqrt(rho), normalised.
+    """
+    n = tuple(int(v) for v in n)
+    dim = len(n)
+    shape = tuple(reversed(n))
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(shape)
+    b = rng.standard_normal(shape)
+    jj = np.zeros(shape)
+    for d in range(dim):
+        j = np.fft.fftfreq(n[d], d=1.0 / n[d])
+        bs = [1] * dim
+        bs[dim - 1 - d] = n[d]
+        jj = jj + (j ** 2).reshape(bs)
+    jabs = np.sqrt(jj)
+    if kcut is None:
+        kcut = min(n) // 2
+    keep = (jabs >= 1) & (jabs <= kcut)
+    dk = np.where(keep, (a + 1j * b) / np.where(jabs == 0, 1.0, jabs), 0.0)
+    delta = np.fft.ifftn(dk).real
+    delta = delta / np.sqrt((delta ** 2).mean())
+    rho = np.exp(amp * delta - 0.5 * amp * amp)
+    return normalise(np.sqrt(rho).astype(np.complex128), n, box)
+
+
+def _min_image(x, c, L):
+    d = x - c
+    return d - L * np.round(d / L)
+
+
+def gaussian_pair_2d(n=(512, 512), box=(1.0, 1.0), width=0.05, sep=0.3, vel=5.0,
+                     hbar_m=1.0, phase=0.0):
+    """Two Gaussian-profile cores moving towards each other along x.
+
+    Density std `width`*L, centres (0.5 -+ sep/2, 0.5) L, phase gradient
+    +-vel/hbar_m along x (velocity in hbar/m units), relative phase `phase`.
+    """
+    X, Y = _grid_coords(n, box)
+    out = np.zeros(tuple(reversed(n)), dtype=np.complex128)
+    w = width * box[0]
+    for sgn, ph in ((+1.0, 0.0), (-1.0, phase)):
+        cx = (0.5 - sgn * sep / 2.0) * box[0]
+        cy = 0.5 * box[1]
+        dx = _min_image(X, cx, box[0])
+        dy = _min_image(Y, cy, box[1])
+        env = np.exp(-(dx ** 2 + dy ** 2) / (4.0 * w * w))
+        out = out + env * np.exp(1j * (sgn * vel * dx / hbar_m + ph))
+    return normalise(out, n, box)
+
+
+def soliton_3d(n=(64, 64, 64), box=(1.0, 1.0, 1.0), core=0.1):
+    """Ground-state-like core profile rho ~ [1 + 0.091 (r/r_c)^2]^-8, r_c = core*L."""
+    X, Y, Z = _grid_coords(n, box)
+    r2 = (_min_image(X, 0.5 * box[0], box[0]) ** 2 + _min_image(Y, 0.5 * box[1], box[1]) ** 2
+          + _min_image(Z, 0.5 * box[2], box[2]) ** 2)
+    rc = core * box[0]
+    rho = (1.0 + 0.091 * r2 / (rc * rc)) ** -8
+    return normalise(np.sqrt(rho).astype(np.complex128), n, box)
+
+
+def random_field(n, seed=0):
+    """Generic smooth-plus-rough complex test field (for parity on small grids)."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(tuple(int(v) for v in n)))
+    psi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape) + 2.0
+    return psi
+
+
+# Named workloads --------------------------------------------------------------
+WORKLOADS = {
+    "1d_n256": dict(n=(256,), box=(1.0,), n_real=64, n_tot=1e4, dt=1e-4, nsteps=1000,
+                    hbar_m=1.0, G=1.0, m_tot=1.0),
+    "2d_n512_pair": dict(n=(512, 512), box=(1.0, 1.0), n_real=256, n_tot=1e6, dt=1e-4,
+                         nsteps=5000, hbar_m=1.0, G=1.0, m_tot=1.0),
+    "3d_n128_grf": dict(n=(128, 128, 128), box=(1.0, 1.0, 1.0), n_real=64,
+                        n_tot=1e3 * 128 ** 3, dt=1e-4, nsteps=2000, hbar_m=1.0, G=1.0, m_tot=1.0),
+}
+
+
+def initial_field(name, n=None):
+    """The coherent (classical) field of a named workload, optionally regenerated at grid n."""
+    w = WORKLOADS[name]
+    n = tuple(n) if n is not None else w["n"]
+    box = w["box"][: len(n)]
+    if name == "1d_n256":
+        return lognormal_field(n, box, seed=0)
+    if name == "2d_n512_pair":
+        return gaussian_pair_2d(n, box, hbar_m=w["hbar_m"])
+    if name == "3d_n128_grf":
+        return lognormal_field(n, box, kcut=min(32, min(n) // 2), seed=0)
+    raise KeyError(name)

@@ -1,0 +1,195 @@
+"""Pins for the oracle's transforms and split-step evolution.
+
+Each check is fixed by mathematics independent of the oracle's own code:
+the DFT summed from its definition, exact solutions of the free Schrodinger
+equation, the closed-form potential of a cosine density, the linear Jeans
+dispersion of the Schrodinger-Poisson system, and the conservation laws and
+time-reversal symmetry of the symplectic Strang splitting (Sec. "Integrating
+the equations of motion").
+"""
+import numpy as np
+import pytest
+
+from oracle import twa_oracle as tw
+from paper_2310_07119_amd import inputs
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
+
+
+# ----------------------------------------------------------------- transforms
+@pytest.mark.parametrize("n", [(8,), (16,), (8, 16), (16, 8), (8, 8, 8), (4, 8, 16)])
+def test_fft_equals_naive_dft(n):
+    grid = tw.Grid(n, (1.0,) * len(n))
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((3,) + grid.shape) + 1j * rng.standard_normal((3,) + grid.shape)
+    fast, slow = tw.Transform(grid, "fft"), tw.Transform(grid, "naive")
+    assert rel(fast.fwd(f), slow.fwd(f)) < 1e-13
+    assert rel(fast.inv(f), slow.inv(f)) < 1e-13
+    assert rel(fast.inv(fast.fwd(f)), f) < 1e-14
+
+
+def test_dft_delta_constant_and_parseval():
+    grid = tw.Grid((8, 16), (1.0, 1.0))
+    T = tw.Transform(grid, "naive")
+    delta = np.zeros(grid.shape, complex)
+    delta[0, 0] = 1.0
+    assert np.allclose(T.fwd(delta), 1.0, atol=1e-14)
+    const = np.ones(grid.shape, complex)
+    F = T.fwd(const)
+    assert abs(F[0, 0] - grid.ncell) < 1e-12 and np.abs(F).sum() - grid.ncell < 1e-9
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal(grid.shape) + 1j * rng.standard_normal(grid.shape)
+    assert abs((np.abs(f) ** 2).sum() - (np.abs(T.fwd(f)) ** 2).sum() / grid.ncell) < 1e-12 * grid.ncell
+
+
+def test_wavenumbers_fft_order():
+    grid = tw.Grid((8,), (2.0,))
+    k = grid.k_axis(0)
+    assert np.allclose(k, np.pi * np.array([0, 1, 2, 3, -4, -3, -2, -1]))
+
+
+@pytest.mark.parametrize("n", [(16,), (8, 8), (4, 8, 8)])
+def test_step_naive_equals_fft(n):
+    grid = tw.Grid(n, (1.0,) * len(n))
+    psi = inputs.random_field(n, seed=4)[None] * 0.3
+    a = tw.evolve(tw.Problem(grid, 1.0, 3.0, 2.0, "fft"), psi, 5, 1e-3)
+    b = tw.evolve(tw.Problem(grid, 1.0, 3.0, 2.0, "naive"), psi, 5, 1e-3)
+    assert rel(a, b) < 1e-12
+
+
+# --------------------------------------------------------- exact solutions
+def test_plane_wave_phase_is_exact():
+    grid = tw.Grid((32, 16), (1.0, 2.0))
+    prob = tw.Problem(grid, hbar_m=0.7, G=5.0, m_tot=3.0)
+    X = np.arange(32)[None, :] / 32.0
+    Y = np.arange(16)[:, None] * (2.0 / 16)
+    kx, ky = 2 * np.pi * 3, 2 * np.pi * (-2) / 2.0
+    psi0 = np.exp(1j * (kx * X + ky * Y)) / np.sqrt(grid.volume)
+    nsteps, dt = 40, 1e-3
+    psi = tw.evolve(prob, psi0, nsteps, dt)
+    expect = psi0 * np.exp(-1j * prob.hbar * (kx ** 2 + ky ** 2) * nsteps * dt / 2.0)
+    assert np.max(np.abs(psi - expect)) < 1e-13 * np.max(np.abs(psi0)) * 10
+
+
+def _free_packet_1d(x, t, L, sigma, x0, k0, hbar, images=6):
+    """Periodised exact free evolution of a Gaussian packet."""
+    a = 1.0 + 1j * hbar * t / (2 * sigma ** 2)
+    out = np.zeros_like(x, dtype=complex)
+    for m in range(-images, images + 1):
+        xm = x + m * L
+        out += (np.exp(-(xm - x0 - hbar * k0 * t) ** 2 / (4 * sigma ** 2 * a)
+                       + 1j * k0 * (xm - x0) - 1j * hbar * k0 ** 2 * t / 2) / np.sqrt(a))
+    return out * (2 * np.pi * sigma ** 2) ** -0.25
+
+
+def test_free_gaussian_packet_1d():
+    L, n = 1.0, 256
+    grid = tw.Grid((n,), (L,))
+    prob = tw.Problem(grid, hbar_m=0.5, G=0.0)
+    x = np.arange(n) * L / n
+    sig, x0, k0 = 0.05, 0.4, 2 * np.pi * 4.3
+    psi0 = _free_packet_1d(x, 0.0, L, sig, x0, k0, prob.hbar)
+    nsteps, dt = 50, 2e-4
+    psi = tw.evolve(prob, psi0, nsteps, dt)
+    exact = _free_packet_1d(x, nsteps * dt, L, sig, x0, k0, prob.hbar)
+    assert rel(psi, exact) < 1e-12
+
+
+def test_free_gaussian_packet_2d_product():
+    L, n = 1.0, (64, 32)
+    grid = tw.Grid(n, (L, L))
+    prob = tw.Problem(grid, hbar_m=1.0, G=0.0)
+    x = np.arange(64) / 64.0
+    y = np.arange(32) / 32.0
+    sx, sy = 0.06, 0.08
+    f = lambda t: (_free_packet_1d(y, t, L, sy, 0.5, -2 * np.pi, 1.0)[:, None]
+                   * _free_packet_1d(x, t, L, sx, 0.3, 2 * np.pi * 2, 1.0)[None, :])
+    psi = tw.evolve(prob, f(0.0), 20, 5e-4)
+    assert rel(psi, f(20 * 5e-4)) < 1e-12
+
+
+# ---------------------------------------------------------------- Poisson
+def test_poisson_cosine_closed_form():
+    grid = tw.Grid((32, 16, 8), (1.0, 2.0, 0.5))
+    prob = tw.Problem(grid, G=2.5)
+    Z, Y, X = np.meshgrid(np.arange(8) * 0.5 / 8, np.arange(16) * 2.0 / 16,
+                          np.arange(32) / 32.0, indexing="ij")
+    kvec = (2 * np.pi * 3, 2 * np.pi * 1 / 2.0, 2 * np.pi * 2 / 0.5)
+    arg = kvec[0] * X + kvec[1] * Y + kvec[2] * Z
+    rho = 7.0 + 0.3 * np.cos(arg)
+    V = tw.potential(prob, rho)
+    k2 = sum(k * k for k in kvec)
+    assert np.max(np.abs(V - (-4 * np.pi * prob.G * 0.3 * np.cos(arg) / k2))) < 1e-13
+    assert abs(V.mean()) < 1e-15
+
+
+def test_uniform_density_no_force_and_kick_preserves_modulus():
+    grid = tw.Grid((16, 16), (1.0, 1.0))
+    prob = tw.Problem(grid, G=10.0)
+    assert np.max(np.abs(tw.potential(prob, np.full(grid.shape, 3.3)))) < 1e-14
+    psi = inputs.random_field((16, 16), seed=8)
+    V = np.random.default_rng(0).standard_normal(grid.shape) * 50
+    out = tw.kick(prob, psi, V, 1e-2)
+    assert np.max(np.abs(np.abs(out) - np.abs(psi))) < 1e-14 * np.max(np.abs(psi)) * 10
+
+
+@pytest.mark.parametrize("m_tot,kind", [(20.0, "oscillate"), (40.0, "grow")])
+def test_linear_jeans_dispersion(m_tot, kind):
+    """Small density mode on a uniform background: omega^2 = (hbar k^2/2)^2 - 4 pi G rho_bar."""
+    L, n = 1.0, 64
+    grid = tw.Grid((n,), (L,))
+    prob = tw.Problem(grid, hbar_m=1.0, G=1.0, m_tot=m_tot)
+    x = np.arange(n) / n
+    k = 2 * np.pi / L
+    eps = 1e-6
+    psi0 = (1 + eps * np.cos(k * x)).astype(complex) / np.sqrt(L)
+    rho_bar = m_tot / L
+    w2 = (prob.hbar * k * k / 2) ** 2 - 4 * np.pi * prob.G * rho_bar
+    dt, nsteps = 1e-4, 1500
+    psi = tw.evolve(prob, psi0, nsteps, dt)
+    t = nsteps * dt
+    contrast = (np.abs(psi) ** 2) * L - 1.0
+    amp = 2 * np.sum(contrast * np.cos(k * x)) / n        # coefficient of cos(kx)
+    expect = 2 * eps * (np.cos(np.sqrt(w2) * t) if w2 > 0 else np.cosh(np.sqrt(-w2) * t))
+    assert (w2 > 0) == (kind == "oscillate")
+    assert abs(amp - expect) < 2e-3 * abs(2 * eps) * max(1.0, abs(expect / (2 * eps)))
+    # and it is NOT the free (G=0) answer
+    free = 2 * eps * np.cos(prob.hbar * k * k / 2 * t)
+    assert abs(free - expect) > 50 * abs(amp - expect)
+
+
+# --------------------------------------------------- conservation / symmetry
+def _nonlinear_1d():
+    grid = tw.Grid((128,), (1.0,))
+    prob = tw.Problem(grid, hbar_m=0.05, G=1.0, m_tot=5.0)
+    psi0 = inputs.lognormal_field((128,), (1.0,), seed=3)
+    return prob, psi0
+
+
+def test_norm_conserved():
+    prob, psi0 = _nonlinear_1d()
+    psi = tw.evolve(prob, psi0, 1000, 1e-3)
+    assert abs(tw.norm(prob, psi) - tw.norm(prob, psi0)) < 1e-12
+
+
+def test_energy_error_second_order():
+    grid = tw.Grid((128,), (1.0,))
+    prob = tw.Problem(grid, hbar_m=0.05, G=1.0, m_tot=5.0)
+    psi0 = inputs.lognormal_field((128,), (1.0,), kcut=6, seed=3)
+    T = 0.4
+    errs = []
+    for nst in (100, 200, 400):
+        psi = tw.evolve(prob, psi0, nst, T / nst)
+        errs.append(abs(tw.energy(prob, psi) - tw.energy(prob, psi0)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.8 < r1 < 4.2 and 3.8 < r2 < 4.2, errs
+
+
+def test_time_reversal():
+    prob, psi0 = _nonlinear_1d()
+    fwd = tw.evolve(prob, psi0, 300, 1e-3)
+    back = tw.evolve(prob, fwd, 300, -1e-3)
+    assert rel(back, psi0) < 1e-11
+    assert rel(fwd, psi0) > 1e-2
