@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the truncated-Wigner ensemble hot path on one MI355X.
+
+One timed run = the whole method on the 2D workload (512^2 grid, 256 Wigner
+realizations plus the classical field, FP64): Wigner sampling, K leapfrog
+steps (drift / Poisson / kick / drift, Sec. "Integrating the equations of
+motion") and the ensemble moments including energies. The metric is
+realization*cell*steps per second. Prints ONE JSON line on stdout.
+
+Extra objects in the line:
+  roofline      the dominant kernel's algorithmic HBM bytes per launch over its
+                average duration (HIP events on the launch stream, same timed run)
+  cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the workload
+  fp32_split    the FP32-split form on the same workload, with its normwise error
+                against the FP64 run for each per-cell moment
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "realization·cell·steps/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(kind, elem, ncell, nfield, n_real):
+    """Algorithmic (compulsory) HBM bytes of one launch of a kernel kind: every
+    input read once and every output written once."""
+    npairs = (nfield + 1) // 2
+    f = elem * ncell * nfield      # all fields once
+    z = elem * ncell * npairs      # spectral scratch once (one complex field per pair)
+    return {
+        "pass_drift": 2 * f,
+        "pass_drift_rho": 2 * f + z,
+        "pass_zfwd": 2 * z, "pass_zinv": 2 * z, "pass_zpoisson": 2 * z,
+        "pass_kick_drift": z + 2 * f,
+        "pass_rho": f + z,
+        "pass_kin_sum": f,
+        "pass_pot_sum": z + f,
+        "step1d_resident": 2 * f,
+        "sample": 16 * ncell + elem * ncell * n_real,
+        "moments": elem * ncell * nfield + 40 * ncell,
+    }.get(kind)
+
+
+def run_gpu(wl, precision, steps, warmup, seed=20231007):
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision=precision)
+    dev = torch.device("cuda:0")
+    plan = Plan(p)
+    cl64 = torch.from_numpy(inputs.initial_field(wl["name"])).to(dev)
+    psi = plan.empty_ensemble(dev)
+    clt = torch.empty(p.shape, dtype=p.cdtype, device=dev)
+    dt = wl["dt"]
+
+    def one_run(k):
+        plan.sample(cl64, seed, 0, out=psi)
+        clt.copy_(cl64.to(p.cdtype))
+        plan.step(psi, k, dt, clt)
+        return plan.moments(psi, clt, energy=True)
+
+    if warmup > 0:
+        one_run(warmup)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mom = one_run(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile()
+    plan.set_profiling(False)
+    elapsed = t1 - t0
+    work = p.n_real * p.ncell * steps
+    res = dict(value=work / elapsed, ms_per_step=1e3 * elapsed / steps, elapsed_s=elapsed, prof=prof,
+               mom={k: (v.double().cpu() if torch.is_tensor(v) else v) for k, v in mom.items()},
+               problem=p)
+    # dominant kernel
+    elem = 16 if precision == "fp64" else 8
+    nfield = p.n_real + 1
+    best = max(prof.items(), key=lambda kv: kv[1][1])
+    kind, (launches, total_ms) = best
+    avg_s = total_ms / launches / 1e3
+    nbytes = pass_bytes(kind, elem, p.ncell, nfield, p.n_real)
+    achieved = nbytes / avg_s / 1e9 if nbytes else None
+    res["roofline"] = {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                       "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches}
+    res["kernel_ms"] = {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(wl, budget_s=15.0, n_sample_real=4, seed=20231007):
+    """The oracle as it stands, on a bounded sample: n_sample_real realizations of
+    the full grid, as many steps as fit in about budget_s seconds."""
+    from oracle import twa_oracle as tw
+    from paper_2310_07119_amd import inputs
+
+    grid = tw.Grid(wl["n"], wl["box"])
+    prob = tw.Problem(grid, wl["hbar_m"], wl["G"], wl["m_tot"])
+    psi_cl = inputs.initial_field(wl["name"])
+    psi = tw.sample(grid, psi_cl, n_sample_real, wl["n_tot"], seed)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        psi = tw.step(prob, psi, wl["dt"])
+        steps += 1
+        if time.perf_counter() - t0 > budget_s and steps >= 2:
+            break
+    el = time.perf_counter() - t0
+    return {"value": n_sample_real * grid.ncell * steps / el, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample_real} realizations x {steps} leapfrog steps of the {wl['name']} grid "
+                      f"{'x'.join(map(str, wl['n']))} (numpy FP64, single thread), {el:.1f} s"}
+
+
+def rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="2d_n512_pair")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): realizations "
+              "are independent, so a multi-GPU run is N copies of this one with disjoint realization offsets "
+              "and no per-step communication; no multi-GPU figure is produced.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2310_07119_amd import inputs
+    wl = dict(inputs.WORKLOADS[args.workload], name=args.workload)
+    log(f"workload {args.workload}: grid {wl['n']}, {wl['n_real']} realizations, {args.precision}, "
+        f"{args.steps} timed steps after {args.warmup} warmup")
+    main_run = run_gpu(wl, args.precision, args.steps, args.warmup)
+    log(f"main: {main_run['value']:.4e} {METRIC}, {main_run['ms_per_step']:.3f} ms/step; "
+        f"kernels {main_run['kernel_ms']}")
+    out = {
+        "metric": METRIC, "value": main_run["value"], "unit": METRIC, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(wl["n"]), "box": list(wl["box"]),
+                   "n_real": wl["n_real"], "n_tot": wl["n_tot"], "dt": wl["dt"], "hbar_m": wl["hbar_m"],
+                   "G": wl["G"], "m_tot": wl["m_tot"], "precision": args.precision,
+                   "timed": "tw_sample + K tw_step leapfrog steps + tw_moments (with energies)",
+                   "classical_field": "evolved alongside, not counted in the work"},
+        "roofline": main_run["roofline"],
+        "kernel_ms": main_run["kernel_ms"],
+    }
+    if not args.no_fp32 and args.precision == "fp64":
+        r32 = run_gpu(wl, "fp32", args.steps, args.warmup)
+        m64, m32 = main_run["mom"], r32["mom"]
+        out["fp32_split"] = {
+            "value": r32["value"], "ms_per_step": r32["ms_per_step"], "speedup": r32["value"] / main_run["value"],
+            "roofline_frac": r32["roofline"]["frac"], "kernel": r32["roofline"]["kernel"],
+            "err_vs_fp64": {k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")},
+        }
+        log(f"fp32: {r32['value']:.4e}, errors {out['fp32_split']['err_vs_fp64']}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+        log(f"cpu oracle: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

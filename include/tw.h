@@ -1,0 +1,152 @@
+/*
+ * tw.h - C ABI of the MI355X truncated-Wigner Schrodinger-Poisson ensemble library.
+ *
+ * The method (arXiv 2310.07119, Sec. "Truncated Wigner approximation"): an
+ * ensemble of independent classical fields psi'_i is drawn from the Wigner
+ * function of a coherent state (Sec. "Initial conditions generation",
+ * Eq. (sample)), each field is advanced by the pseudo-spectral symplectic
+ * leapfrog of Sec. "Integrating the equations of motion" for the normalised
+ * Schrodinger-Poisson system of Eq. (mft_normed)
+ *     i d_t psi' = (-hbar/2 lap + V/hbar) psi',   lap V = 4 pi G M_tot |psi'|^2,
+ * and quantum expectation values are ensemble averages of Weyl symbols
+ * (Sec. "Evaluating operators", Eq. (Q)).
+ *
+ * Conventions shared by every call
+ *  - All functions are plain C, thread-compatible (one plan per thread or
+ *    external locking), return a tw_status and never print. On failure
+ *    tw_last_error() returns a message for the calling thread.
+ *  - Array arguments are DEVICE pointers owned by the caller; the library never
+ *    frees them. They must be contiguous and aligned to the complex element
+ *    (16 bytes for complex128, 8 bytes for complex64), else TW_ELAYOUT.
+ *  - Field layout: row-major [realization][z][y][x], x fastest, complex values
+ *    interleaved (re, im). A TW_FP64 plan stores complex128; a TW_FP32_SPLIT
+ *    plan stores complex64 fields (FP32 transforms, FP64 phase arguments,
+ *    FP64 Poisson zero mode and FP64 diagnostics).
+ *  - Fields are the normalised psi' of Eq. (mft_normed): sum_g |psi'_g|^2 dV = 1,
+ *    mass density rho = m_tot |psi'|^2.
+ *  - `stream` is a hipStream_t passed as void* (NULL = legacy default stream);
+ *    every device call is enqueued on it and the call returns without waiting.
+ *    Device faults surface as TW_EHIP on a later call.
+ */
+#ifndef TW_H
+#define TW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TW_OK = 0,
+  TW_EINVAL = -1,        /* bad argument value (NULL plan, n<1, dt not finite, ...) */
+  TW_EUNSUPPORTED = -2,  /* valid but not implemented (grid size, dimension) */
+  TW_ELAYOUT = -3,       /* misaligned pointer */
+  TW_EHIP = -4,          /* HIP runtime error (launch failure, earlier device fault) */
+  TW_ENOMEM = -5         /* device workspace allocation failed */
+} tw_status;
+
+typedef enum { TW_FP64 = 0, TW_FP32_SPLIT = 1 } tw_precision;
+
+/* Problem statement: grid x_g = g dx, g in {0..n-1}^D (Sec. "Initial conditions
+ * generation"); physical parameters of Eq. (mft_normed); n_tot is the
+ * sampling particle number n^s_tot that sets the noise amplitude only
+ * (Sec. "Estimating the breaktime"). */
+typedef struct {
+  int32_t dim;        /* D in {1,2,3} */
+  int32_t n[3];       /* points per axis, x first; unused axes must be 1.
+                         Supported: powers of two, 16..1024 (D=1: 8..1024) */
+  double box[3];      /* box length per axis, > 0 (unused axes ignored) */
+  double hbar_m;      /* hbar/m > 0 */
+  double G;           /* Newton constant >= 0 (0 = free Schrodinger equation) */
+  double m_tot;       /* total mass M_tot > 0 */
+  double n_tot;       /* sampling particle number > 0 (may be +inf: no noise) */
+  int64_t n_real;     /* number of realizations N_s >= 1 */
+  int32_t precision;  /* tw_precision */
+  int32_t reserved;   /* must be 0 */
+} tw_problem;
+
+typedef struct tw_plan_s* tw_plan;
+
+/* Create a plan: validates the problem, builds twiddle and wavenumber tables
+ * and allocates the device workspace (about half a field per realization for
+ * D >= 2). Synchronous. Uses the current HIP device. */
+int tw_plan_create(const tw_problem* problem, tw_plan* out);
+
+/* Release the plan and its workspace. Waits for the device. NULL is a no-op. */
+int tw_plan_destroy(tw_plan plan);
+
+/* Wigner sampling (Eq. (sample)). For every realization r in [0, n_real) and
+ * cell g: psi[r][g] = psi_cl[g] + (z1 + i z2) * 0.5 / sqrt(n_tot dV), with
+ * (z1, z2) standard normal from Philox4x64-10 at counter (g, real_offset + r,
+ * 0, 0), key (seed, 0x5457), mapped by the Box-Muller transform written as a
+ * fixed sequence of correctly rounded double operations (series logarithm and
+ * sine/cosine after exact range reduction, no fused multiply-add).
+ *   psi_cl : device, [N] complex128 (always FP64), the coherent field.
+ *   psi    : device, [n_real][N] complex128 (TW_FP64) or complex64
+ *            (TW_FP32_SPLIT: the FP64 sample rounded to nearest).
+ * Results are bit-reproducible from (seed, real_offset + r, g). */
+int tw_sample(tw_plan plan, const void* psi_cl, uint64_t seed, int64_t real_offset,
+              void* psi, void* stream);
+
+/* Advance every field by nsteps leapfrog steps of size dt (Sec. "Integrating
+ * the equations of motion"): half drift exp(-i hbar |k|^2 dt/4) in Fourier
+ * space, potential V_k = -4 pi G rho_k / |k|^2 (zero mode removed) from the
+ * drifted field's own density, kick exp(-i dt V / hbar), half drift.
+ * Adjacent half drifts inside one call are merged; the state on return is
+ * exactly that after nsteps complete steps.
+ *   psi           : device, [n_real][N] fields in the plan's precision, in place.
+ *   psi_classical : device, [N] one extra field in the plan's precision that is
+ *                   evolved alongside (the noise-free classical run), or NULL.
+ * nsteps >= 0; dt finite (negative dt runs backwards). */
+int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt,
+            void* stream);
+
+/* Outputs of tw_moments. Every pointer is a caller-owned device array and may
+ * be NULL to skip that output. */
+typedef struct {
+  void* mean_psi;     /* [N] complex128: <psi'>_g */
+  double* mean_abs2;  /* [N] <|psi'|^2>_g, Weyl (symmetric) ordering */
+  double* mean_rho;   /* [N] <rho>_g = m_tot <|psi'|^2>_g */
+  double* var_rho;    /* [N] <(rho - <rho>)^2>_g, plug-in 1/N_s estimator */
+  double* norm;       /* [n_real] sum_g |psi'|^2 dV per realization */
+  double* energy;     /* [n_real] m_tot [ (hbar^2/2) int|grad psi'|^2 + (1/2) int V|psi'|^2 ] */
+  double* scalars;    /* [8]: Q_raw, Q_sym, dev_rho_L1, dev_psi_L2, energy_mean,
+                         norm_mean, nonfinite_count, energy_classical */
+} tw_moments_out;
+
+/* Ensemble moments (Sec. "Evaluating operators"; Eq. (Q)):
+ *   Q_raw = sum_g dV (<|psi'|^2> - |<psi'>|^2);  Q_sym = Q_raw - N/(2 n_tot);
+ *   dev_rho_L1 = sum_g dV |<rho> - rho_cl| / m_tot;  dev_psi_L2 = sum_g dV |<psi'> - psi'_cl|^2
+ * (the two deviations need psi_classical, else they are 0); nonfinite_count
+ * counts realizations holding a NaN or Inf. All sums are FP64. energy and
+ * scalars[4], scalars[7] are computed only when `energy` is non-NULL (they need
+ * one spectral transform and one Poisson solve per realization).
+ *   psi           : device, [n_real][N] in the plan's precision.
+ *   psi_classical : device, [N] in the plan's precision, or NULL. */
+int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
+               const tw_moments_out* out, void* stream);
+
+/* Kernel timing for measurement tools (not needed for the method itself).
+ * When enabled, every kernel launched by tw_sample / tw_step / tw_moments on
+ * this plan is bracketed by two HIP events recorded on the launch stream.
+ * Kernel kinds are numbered 0 .. TW_NUM_KERNEL_KINDS-1 (tw_kernel_kind_name). */
+#define TW_NUM_KERNEL_KINDS 16
+int tw_plan_set_profiling(tw_plan plan, int32_t enable);
+
+/* Waits for the recorded events, writes for each kind k < n_kinds the number
+ * of launches[k] and their summed device time total_ms[k] since the last call,
+ * then clears the record. Host arrays of n_kinds elements owned by the caller. */
+int tw_plan_get_profile(tw_plan plan, int32_t n_kinds, int64_t* launches, double* total_ms);
+
+/* Static name of kernel kind k ("" outside the range). */
+const char* tw_kernel_kind_name(int32_t kind);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* tw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TW_H */

@@ -1,0 +1,456 @@
+// C ABI: plan management, argument validation and the launch sequences of
+// tw_sample / tw_step / tw_moments (declared in include/tw.h).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tw {
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define TW_HIP(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(TW_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// ----------------------------------------------------------- kernel timing
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+struct Prof {
+  std::vector<ProfRec> recs;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+};
+
+const char* const kKindNames[KIND_COUNT] = {
+    "pass_drift", "pass_drift_rho", "pass_zfwd", "pass_zpoisson", "pass_zinv", "pass_kick_drift",
+    "pass_rho", "pass_kin_sum", "pass_pot_sum", "step1d_resident", "sample", "moments",
+    "tables", "field_mean", "energy_finalize", "unused"};
+
+// Run launcher f; when profiling, bracket it with events on stream s.
+template <class F>
+hipError_t timed(Plan& P, int kind, hipStream_t s, F&& f) {
+  if (!P.profiling) return f();
+  Prof* pr = static_cast<Prof*>(P.prof);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!pr->pool.empty()) {
+    ev = pr->pool.back();
+    pr->pool.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(ev.first, s);
+  if (e != hipSuccess) return e;
+  e = f();
+  hipError_t e2 = hipEventRecord(ev.second, s);
+  pr->recs.push_back({kind, ev.first, ev.second});
+  return e != hipSuccess ? e : e2;
+}
+
+int64_t axis_stride(const Plan& P, int axis) {
+  if (axis == 0) return 1;
+  if (axis == 1) return P.n[0];
+  return (int64_t)P.n[0] * P.n[1];
+}
+
+void free_plan(Plan* P) {
+  if (!P) return;
+  for (int d = 0; d < 3; ++d) {
+    if (P->twd[d]) (void)hipFree(P->twd[d]);
+    if (P->k2[d]) (void)hipFree(P->k2[d]);
+  }
+  if (P->phase) (void)hipFree(P->phase);
+  if (P->z) (void)hipFree(P->z);
+  if (P->rho_mean) (void)hipFree(P->rho_mean);
+  if (P->partial) (void)hipFree(P->partial);
+  if (P->scratch_small) (void)hipFree(P->scratch_small);
+  if (P->prof) {
+    Prof* pr = static_cast<Prof*>(P->prof);
+    for (auto& r : pr->recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto& r : pr->pool) {
+      (void)hipEventDestroy(r.first);
+      (void)hipEventDestroy(r.second);
+    }
+    delete pr;
+  }
+  delete P;
+}
+
+int check_ptr(const Plan& P, const void* p, const char* name, bool nullable) {
+  if (!p) return nullable ? TW_OK : fail(TW_EINVAL, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) % P.elem != 0)
+    return fail(TW_ELAYOUT, "%s is not aligned to the %zu-byte complex element", name, P.elem);
+  return TW_OK;
+}
+
+// groups (workgroups along x) of a pass along `axis`
+int pass_groups(const Plan& P, int axis) {
+  const int c = pass_pencils_per_group(P.n[axis], P.fp32);
+  const int64_t np = P.ncell / P.n[axis];
+  return (int)((np + c - 1) / c);
+}
+
+PassArgs base_args(const Plan& P, void* psi, void* psi_cl, int64_t nfield) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.psi = psi;
+  a.psi_cl = psi_cl;
+  a.z = P.z;
+  a.n_real = P.p.n_real;
+  a.nfield = nfield;
+  a.ncell = P.ncell;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = P.n[d];
+    a.k2[d] = P.k2[d];
+  }
+  a.green = -4.0 * M_PI * P.p.G / (double)P.ncell;
+  a.m_tot = P.p.m_tot;
+  return a;
+}
+
+hipError_t pass(Plan& P, PassArgs a, int mode, int axis, const void* phase, hipStream_t s) {
+  a.axis = axis;
+  a.stride = axis_stride(P, axis);
+  a.twd = P.twd[axis];
+  a.phase = phase;
+  const int64_t npairs = (a.nfield + 1) / 2;
+  return timed(P, mode, s, [&] { return launch_pass(P, mode, a, s, (int)npairs); });
+}
+
+}  // namespace
+}  // namespace tw
+
+using namespace tw;
+
+extern "C" {
+
+const char* tw_last_error(void) { return g_error.c_str(); }
+
+int tw_plan_create(const tw_problem* pr, tw_plan* out) {
+  if (!pr || !out) return fail(TW_EINVAL, "NULL problem or output pointer");
+  *out = nullptr;
+  if (pr->dim < 1 || pr->dim > 3) return fail(TW_EINVAL, "dim must be 1, 2 or 3 (got %d)", pr->dim);
+  if (pr->reserved != 0) return fail(TW_EINVAL, "reserved field must be 0");
+  if (pr->precision != TW_FP64 && pr->precision != TW_FP32_SPLIT)
+    return fail(TW_EINVAL, "unknown precision %d", pr->precision);
+  for (int d = 0; d < 3; ++d) {
+    if (d < pr->dim) {
+      if (pr->n[d] < 1) return fail(TW_EINVAL, "n[%d] must be positive", d);
+      if (!(pr->box[d] > 0.0) || !std::isfinite(pr->box[d])) return fail(TW_EINVAL, "box[%d] must be > 0", d);
+      if (!is_pow2(pr->n[d])) return fail(TW_EUNSUPPORTED, "n[%d]=%d is not a power of two", d, pr->n[d]);
+      const bool ok = pr->dim == 1 ? step1d_length_supported(pr->n[d]) : pass_length_supported(pr->n[d]);
+      if (!ok) return fail(TW_EUNSUPPORTED, "n[%d]=%d outside the supported lengths", d, pr->n[d]);
+    } else if (pr->n[d] != 1) {
+      return fail(TW_EINVAL, "n[%d] must be 1 for an unused axis", d);
+    }
+  }
+  if (!(pr->hbar_m > 0.0) || !std::isfinite(pr->hbar_m)) return fail(TW_EINVAL, "hbar_m must be > 0");
+  if (!(pr->G >= 0.0) || !std::isfinite(pr->G)) return fail(TW_EINVAL, "G must be >= 0 and finite");
+  if (!(pr->m_tot > 0.0) || !std::isfinite(pr->m_tot)) return fail(TW_EINVAL, "m_tot must be > 0");
+  if (!(pr->n_tot > 0.0)) return fail(TW_EINVAL, "n_tot must be > 0");
+  if (pr->n_real < 1) return fail(TW_EINVAL, "n_real must be >= 1");
+
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return fail(TW_ENOMEM, "host allocation failed");
+  std::memset(static_cast<void*>(P), 0, sizeof(Plan));
+  P->p = *pr;
+  P->dim = pr->dim;
+  P->ncell = 1;
+  P->nmax = 1;
+  double dv = 1.0, vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    P->n[d] = d < pr->dim ? pr->n[d] : 1;
+    P->ncell *= P->n[d];
+    if (P->n[d] > P->nmax) P->nmax = P->n[d];
+    if (d < pr->dim) {
+      dv = dv * (pr->box[d] / pr->n[d]);
+      vol = vol * pr->box[d];
+    }
+  }
+  P->dV = dv;
+  P->volume = vol;
+  P->fp32 = pr->precision == TW_FP32_SPLIT;
+  P->elem = P->fp32 ? 8 : 16;
+  P->nfield = pr->n_real + 1;
+  P->npairs = (P->nfield + 1) / 2;
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    free_plan(P);
+    return fail(TW_EHIP, "no HIP device");
+  }
+
+#define ALLOC(ptr, bytes)                                                               \
+  do {                                                                                  \
+    if (hipMalloc(reinterpret_cast<void**>(&(ptr)), (bytes)) != hipSuccess) {            \
+      free_plan(P);                                                                     \
+      (void)hipGetLastError();                                                          \
+      return fail(TW_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes)); \
+    }                                                                                   \
+  } while (0)
+
+  // twiddle and wavenumber tables per axis
+  for (int d = 0; d < 3; ++d) {
+    const int n = P->n[d];
+    std::vector<double> k2(n);
+    for (int j = 0; j < n; ++j) {
+      const int jj = (j < (n + 1) / 2) ? j : j - n;  // FFT order; Nyquist as -n/2
+      const double k = 2.0 * M_PI * (double)jj / (d < pr->dim ? pr->box[d] : 1.0);
+      k2[j] = d < pr->dim ? k * k : 0.0;
+    }
+    ALLOC(P->k2[d], sizeof(double) * n);
+    if (hipMemcpy(P->k2[d], k2.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
+      free_plan(P);
+      return fail(TW_EHIP, "table upload failed");
+    }
+    std::vector<double> tw2(2 * n);
+    for (int e = 0; e < n; ++e) {
+      const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)n;
+      tw2[2 * e] = (double)cosl(ang);
+      tw2[2 * e + 1] = (double)sinl(ang);
+    }
+    if (P->fp32) {
+      std::vector<float> tf(2 * n);
+      for (int i = 0; i < 2 * n; ++i) tf[i] = (float)tw2[i];
+      ALLOC(P->twd[d], sizeof(float) * 2 * n);
+      if (hipMemcpy(P->twd[d], tf.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(P);
+        return fail(TW_EHIP, "table upload failed");
+      }
+    } else {
+      ALLOC(P->twd[d], sizeof(double) * 2 * n);
+      if (hipMemcpy(P->twd[d], tw2.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(P);
+        return fail(TW_EHIP, "table upload failed");
+      }
+    }
+  }
+  ALLOC(P->phase, sizeof(double) * 2 * 3 * 2 * P->nmax);
+  // spectral scratch: one complex field per pair of realizations (diagnostics
+  // need it in 1D too, where n >= 16)
+  const bool need_z = pr->dim >= 2 || pass_length_supported(P->n[0]);
+  if (need_z) ALLOC(P->z, P->elem * (size_t)P->npairs * (size_t)P->ncell);
+  ALLOC(P->rho_mean, sizeof(double) * P->nfield);
+  int64_t gmax = 1;
+  if (need_z)
+    for (int d = 0; d < pr->dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(*P, d));
+  const int64_t nwaves = (P->ncell + 63) / 64;
+  const int64_t energy_part = 4 * P->nfield * gmax + P->nfield;
+  const int64_t mom_part = pr->n_real * nwaves + 3 * nwaves + pr->n_real + 8;
+  P->partial_len = (size_t)(energy_part + mom_part);
+  ALLOC(P->partial, sizeof(double) * P->partial_len);
+  ALLOC(P->scratch_small, sizeof(double) * 64);
+#undef ALLOC
+  *out = reinterpret_cast<tw_plan>(P);
+  return TW_OK;
+}
+
+int tw_plan_destroy(tw_plan plan) {
+  if (!plan) return TW_OK;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  (void)hipDeviceSynchronize();
+  free_plan(P);
+  return TW_OK;
+}
+
+int tw_sample(tw_plan plan, const void* psi_cl, uint64_t seed, int64_t real_offset, void* psi, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (!psi_cl) return fail(TW_EINVAL, "psi_cl is NULL");
+  if (reinterpret_cast<uintptr_t>(psi_cl) % 16 != 0) return fail(TW_ELAYOUT, "psi_cl is not 16-byte aligned");
+  if (int rc = check_ptr(P, psi, "psi", false)) return rc;
+  if (real_offset < 0) return fail(TW_EINVAL, "real_offset must be >= 0");
+  if (P.p.n_real > 65535) return fail(TW_EUNSUPPORTED, "tw_sample supports at most 65535 realizations per call");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TW_HIP(timed(P, KIND_SAMPLE, s, [&] { return launch_sample(P, psi_cl, seed, real_offset, psi, s); }));
+  return TW_OK;
+}
+
+int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (int rc = check_ptr(P, psi, "psi", false)) return rc;
+  if (int rc = check_ptr(P, psi_cl, "psi_classical", true)) return rc;
+  if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
+  if (nsteps == 0) return TW_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
+  const double h = 0.5 * dt;
+  // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
+  auto phase_slot = [&](int axis, int full) -> void* {
+    return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
+  };
+  for (int d = 0; d < P.dim; ++d) {
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
+  }
+  if (P.fp32)
+    TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
+  const double kick = dt / P.p.hbar_m;
+
+  if (P.dim == 1) {
+    TW_HIP(timed(P, KIND_STEP1D, s, [&] {
+      return launch_step1d(P, psi, psi_cl, nfield, nsteps, phase_slot(0, 0), phase_slot(0, 1), kick, s);
+    }));
+    return TW_OK;
+  }
+
+  PassArgs a = base_args(P, psi, psi_cl, nfield);
+  a.kick = kick;
+  a.rho_mean = P.fp32 ? P.rho_mean : nullptr;
+  const int D = P.dim;
+  int o[3] = {0, 1, 2};
+  // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
+  for (int i = D - 1; i >= 1; --i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 0), s));
+  TW_HIP(pass(P, a, PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0), s));
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const bool last = (st + 1 == nsteps);
+    const int full = last ? 0 : 1;
+    // rest of the forward transform of rho, Green's function, inverse (all but o[0])
+    for (int i = 1; i < D - 1; ++i) TW_HIP(pass(P, a, PASS_ZFWD, o[i], nullptr, s));
+    TW_HIP(pass(P, a, PASS_ZPOISSON, o[D - 1], nullptr, s));
+    for (int i = D - 2; i >= 1; --i) TW_HIP(pass(P, a, PASS_ZINV, o[i], nullptr, s));
+    // last inverse along o[0] -> V, kick, drift along o[0]
+    TW_HIP(pass(P, a, PASS_KICK_DRIFT, o[0], phase_slot(o[0], full), s));
+    if (!last) {
+      for (int i = 1; i < D - 1; ++i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 1), s));
+      TW_HIP(pass(P, a, PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1), s));
+      // reverse the axis order so the density transform just made is the first one
+      int r[3] = {0, 0, 0};
+      for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
+      for (int i = 0; i < D; ++i) o[i] = r[i];
+    } else {
+      for (int i = 1; i < D; ++i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 0), s));
+    }
+  }
+  return TW_OK;
+}
+
+int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_moments_out* out, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  if (!out) return fail(TW_EINVAL, "NULL output struct");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (int rc = check_ptr(P, psi, "psi", false)) return rc;
+  if (int rc = check_ptr(P, psi_cl, "psi_classical", true)) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double* energy_dev = nullptr;
+  if (out->energy) {
+    if (!P.z) return fail(TW_EUNSUPPORTED, "energy needs grid lengths >= 16");
+    const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
+    void* psi_m = const_cast<void*>(psi);
+    void* cl_m = const_cast<void*>(psi_cl);
+    PassArgs a = base_args(P, psi_m, cl_m, nfield);
+    int ng[4] = {1, 1, 1, 1};
+    int64_t gmax = 1;
+    for (int d = 0; d < P.dim; ++d) {
+      ng[d] = pass_groups(P, d);
+      gmax = std::max<int64_t>(gmax, ng[d]);
+    }
+    ng[3] = ng[0];
+    const int64_t gstride = P.nfield * gmax;
+    energy_dev = P.partial + 4 * gstride;
+    if (P.fp32) {
+      TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
+      a.rho_mean = P.rho_mean;
+    }
+    for (int d = 0; d < P.dim; ++d) {
+      PassArgs b = a;
+      b.partial = P.partial + d * gstride;
+      TW_HIP(pass(P, b, PASS_KIN_SUM, d, nullptr, s));
+    }
+    TW_HIP(pass(P, a, PASS_RHO, 0, nullptr, s));
+    for (int d = 1; d < P.dim - 1; ++d) TW_HIP(pass(P, a, PASS_ZFWD, d, nullptr, s));
+    if (P.dim >= 2) TW_HIP(pass(P, a, PASS_ZPOISSON, P.dim - 1, nullptr, s));
+    for (int d = P.dim - 2; d >= 1; --d) TW_HIP(pass(P, a, PASS_ZINV, d, nullptr, s));
+    {
+      PassArgs b = a;
+      b.partial = P.partial + 3 * gstride;
+      b.pot_green = P.dim == 1 ? 1 : 0;
+      TW_HIP(pass(P, b, PASS_POT_SUM, 0, nullptr, s));
+    }
+    TW_HIP(timed(P, KIND_ENERGY, s,
+                 [&] { return launch_energy_finalize(P, P.partial, gstride, nfield, ng, energy_dev, s); }));
+    TW_HIP(hipMemcpyAsync(out->energy, energy_dev, sizeof(double) * P.p.n_real, hipMemcpyDeviceToDevice, s));
+  }
+  Plan Q = P;
+  // the moment reductions use the region after the energy partials
+  {
+    int64_t gmax = 1;
+    if (P.z)
+      for (int d = 0; d < P.dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(P, d));
+    Q.partial = P.partial + 4 * P.nfield * gmax + P.nfield;
+  }
+  TW_HIP(timed(P, KIND_MOMENTS, s, [&] { return launch_moments(Q, psi, psi_cl, out, energy_dev, s); }));
+  return TW_OK;
+}
+
+int tw_plan_set_profiling(tw_plan plan, int32_t enable) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (enable && !P.prof) P.prof = new (std::nothrow) Prof();
+  if (enable && !P.prof) return fail(TW_ENOMEM, "host allocation failed");
+  P.profiling = enable != 0;
+  return TW_OK;
+}
+
+int tw_plan_get_profile(tw_plan plan, int32_t n_kinds, int64_t* launches, double* total_ms) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  if (n_kinds < 0 || (n_kinds > 0 && (!launches || !total_ms))) return fail(TW_EINVAL, "bad output arrays");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  for (int k = 0; k < n_kinds; ++k) {
+    launches[k] = 0;
+    total_ms[k] = 0.0;
+  }
+  if (!P.prof) return TW_OK;
+  Prof* pr = static_cast<Prof*>(P.prof);
+  int rc = TW_OK;
+  for (auto& r : pr->recs) {
+    if (rc == TW_OK) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) rc = fail(TW_EHIP, "event timing failed: %s", hipGetErrorString(e));
+      else if (r.kind >= 0 && r.kind < n_kinds) {
+        launches[r.kind] += 1;
+        total_ms[r.kind] += ms;
+      }
+    }
+    pr->pool.push_back({r.a, r.b});
+  }
+  pr->recs.clear();
+  return rc;
+}
+
+const char* tw_kernel_kind_name(int32_t kind) {
+  if (kind < 0 || kind >= KIND_COUNT) return "";
+  return kKindNames[kind];
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Host-side plan structure and the launchers each kernel translation unit exports.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/tw.h"
+
+namespace tw {
+
+// Arguments of one pencil pass over the ensemble (see kernels_step.hip).
+struct PassArgs {
+  void* psi;               // [n_real][N] fields (plan precision)
+  void* psi_cl;            // extra classical field or nullptr
+  void* z;                 // [npairs][N] spectral density / potential scratch
+  int64_t n_real;
+  int64_t nfield;          // n_real + (psi_cl != nullptr)
+  int64_t ncell;           // N = n0 n1 n2
+  int64_t stride;          // element stride of the pass axis
+  int32_t axis;            // 0, 1, 2
+  int32_t n[3];
+  const void* twd;         // W_n^e table of the pass length, plan precision
+  const void* phase;       // cx<double>[n_axis] drift factor exp(-i hbar k^2 tau/2)/n_axis
+  const double* k2[3];     // per-axis k^2 tables (FFT order)
+  double green;            // -4 pi G / N   (Poisson factor; 1/N of the inverse folded in)
+  double kick;             // dt / hbar
+  double m_tot;
+  const double* rho_mean;  // [nfield] density mean subtracted before the transform, or nullptr
+  double* partial;         // reduction output for diagnostic passes
+  int32_t pot_green;       // PASS_POT_SUM: apply G(k) along the axis before the inverse (D = 1)
+  int32_t pad_;
+};
+
+enum PassMode : int {
+  PASS_DRIFT = 0,       // psi <- IFFT_a(phase * FFT_a psi)
+  PASS_DRIFT_RHO = 1,   // drift, then z <- FFT_a(rho_A - mean_A + i (rho_B - mean_B))
+  PASS_ZFWD = 2,        // z <- FFT_a z
+  PASS_ZPOISSON = 3,    // z <- IFFT_a(G(k) FFT_a z)
+  PASS_ZINV = 4,        // z <- IFFT_a z
+  PASS_KICK_DRIFT = 5,  // V_A + i V_B <- IFFT_a z; psi <- kick; drift
+  PASS_RHO = 6,         // z <- FFT_a(rho_A - mean_A + i (rho_B - mean_B))   (diagnostics)
+  PASS_KIN_SUM = 7,     // partial[f][group] <- sum k_a^2 |FFT_a psi|^2     (diagnostics)
+  PASS_POT_SUM = 8,     // V <- IFFT_a z; partial[f][group] <- sum V |psi|^2 (diagnostics)
+  PASS_NMODES = 9
+};
+
+struct Plan {
+  tw_problem p;
+  int dim;
+  int n[3];
+  int64_t ncell;
+  int64_t nfield;   // n_real + 1 (slot for the classical field)
+  int64_t npairs;   // ceil(nfield / 2)
+  double dV;
+  double volume;
+  bool fp32;
+  size_t elem;      // bytes per complex element
+  int device;
+  // device tables
+  void* twd[3];          // per axis, plan precision
+  double* k2[3];         // per axis
+  void* phase;           // cx<double>[3][2][nmax]: axis, (half, full)
+  int nmax;
+  // workspace
+  void* z;               // [npairs][N] complex scratch (D >= 2)
+  double* rho_mean;      // [nfield]
+  double* partial;       // reductions
+  size_t partial_len;    // doubles
+  double* scratch_small; // [64] misc device scalars
+  // kernel timing (tw_plan_set_profiling)
+  bool profiling;
+  void* prof;            // opaque event record (api.hip)
+};
+
+enum KernelKind : int {
+  KIND_STEP1D = PASS_NMODES,  // 9
+  KIND_SAMPLE = 10,
+  KIND_MOMENTS = 11,
+  KIND_TABLES = 12,
+  KIND_MEAN = 13,
+  KIND_ENERGY = 14,
+  KIND_COUNT = 16
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs_or_fields);
+hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
+                         const void* phase_half, const void* phase_full, double kick, hipStream_t s);
+hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hipStream_t s);
+hipError_t launch_field_mean(const Plan& P, const void* psi, const void* psi_cl, int64_t nfield,
+                             double* out_mean, hipStream_t s);
+hipError_t launch_sample(const Plan& P, const void* psi_cl, uint64_t seed, int64_t real_offset,
+                         void* psi, hipStream_t s);
+hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t gstride, int64_t nfield,
+                                  const int ng[4], double* out, hipStream_t s);
+hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
+                          const double* energy_dev, hipStream_t s);
+
+// Supported transform lengths and the pencils a pass workgroup holds.
+bool pass_length_supported(int n);
+int pass_pencils_per_group(int n, bool fp32);
+bool step1d_length_supported(int n);
+
+}  // namespace tw

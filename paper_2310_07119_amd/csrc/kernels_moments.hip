@@ -1,0 +1,218 @@
+// Ensemble moments (Sec. "Evaluating operators": <Omega> ~ (1/N_s) sum_i Omega_W[psi_i];
+// Eq. (Q) for the quantumness). One pass over the ensemble, one thread per cell,
+// realizations read in turn so every load is coalesced along x; all sums FP64.
+// Second moments are accumulated about the first realization's value (shifted
+// sums), which keeps the variance free of cancellation when the noise is small.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tw {
+
+struct MomArgs {
+  const void* psi;
+  const void* psi_cl;
+  int64_t n_real;
+  int64_t ncell;
+  double m_tot;
+  double dV;
+  cx<double>* mean_psi;
+  double* mean_abs2;
+  double* mean_rho;
+  double* var_rho;
+  double* wave_norm;  // [n_real][nwaves]
+  double* wave_q;     // [3][nwaves]: Q, dev_rho, dev_psi
+  int64_t nwaves;
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) moments_cell_kernel(MomArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = g < a.ncell;
+  const int64_t wave = g >> 6;
+  const int lane = threadIdx.x & 63;
+  const cx<T>* psi = reinterpret_cast<const cx<T>*>(a.psi);
+
+  cx<double> c0 = {0.0, 0.0};
+  double k0 = 0.0;
+  double s_a2 = 0.0, sd_a2 = 0.0, sdd_a2 = 0.0, sdd = 0.0;
+  cx<double> sd = {0.0, 0.0};
+  for (int64_t r = 0; r < a.n_real; ++r) {
+    cx<double> v = {0.0, 0.0};
+    if (active) {
+      const cx<T> w = psi[r * a.ncell + g];
+      v = {(double)w.re, (double)w.im};
+    }
+    const double a2 = v.re * v.re + v.im * v.im;
+    if (r == 0) {
+      c0 = v;
+      k0 = a2;
+    }
+    s_a2 += a2;
+    const double da = a2 - k0;
+    sd_a2 += da;
+    sdd_a2 += da * da;
+    const cx<double> d = v - c0;
+    sd = sd + d;
+    sdd += d.re * d.re + d.im * d.im;
+    const double wn = wave_sum(a2);
+    if (lane == 0 && wave < a.nwaves) a.wave_norm[r * a.nwaves + wave] = wn;
+  }
+  const double inv = 1.0 / (double)a.n_real;
+  const cx<double> m1 = {c0.re + sd.re * inv, c0.im + sd.im * inv};
+  const double m2 = s_a2 * inv;
+  const double mda = sd_a2 * inv;
+  const double var_a2 = sdd_a2 * inv - mda * mda;
+  const double var_psi = sdd * inv - (sd.re * sd.re + sd.im * sd.im) * inv * inv;
+  double q = 0.0, dr = 0.0, dp = 0.0;
+  if (active) {
+    if (a.mean_psi) a.mean_psi[g] = m1;
+    if (a.mean_abs2) a.mean_abs2[g] = m2;
+    if (a.mean_rho) a.mean_rho[g] = a.m_tot * m2;
+    if (a.var_rho) a.var_rho[g] = a.m_tot * a.m_tot * var_a2;
+    q = var_psi * a.dV;
+    if (a.psi_cl) {
+      const cx<T> w = reinterpret_cast<const cx<T>*>(a.psi_cl)[g];
+      const cx<double> cl = {(double)w.re, (double)w.im};
+      dr = fabs(m2 - (cl.re * cl.re + cl.im * cl.im)) * a.dV;
+      const cx<double> e = m1 - cl;
+      dp = (e.re * e.re + e.im * e.im) * a.dV;
+    }
+  }
+  q = wave_sum(q);
+  dr = wave_sum(dr);
+  dp = wave_sum(dp);
+  if (lane == 0 && wave < a.nwaves) {
+    a.wave_q[wave] = q;
+    a.wave_q[a.nwaves + wave] = dr;
+    a.wave_q[2 * a.nwaves + wave] = dp;
+  }
+}
+
+// Sum `len` doubles at src + b*len for block b; result * scale to dst[b].
+__global__ void __launch_bounds__(256) row_sum_kernel(const double* __restrict__ src, int64_t len, double scale,
+                                                      double* __restrict__ dst) {
+  __shared__ double red[4];
+  const int64_t b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) s += src[b * len + i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) dst[b] = (red[0] + red[1] + red[2] + red[3]) * scale;
+}
+
+// scalars: [0] Q_raw [1] Q_sym [2] dev_rho_L1 [3] dev_psi_L2 [4] energy mean
+// [5] norm mean [6] nonfinite count [7] classical energy
+__global__ void __launch_bounds__(256) scalars_kernel(const double* __restrict__ qsum /*[3]*/,
+                                                      const double* __restrict__ norms, const double* __restrict__ energy,
+                                                      int64_t n_real, double vacuum, int have_cl, int have_energy,
+                                                      double* __restrict__ out) {
+  __shared__ double red[3][4];
+  double sn = 0.0, se = 0.0, nf = 0.0;
+  for (int64_t r = threadIdx.x; r < n_real; r += blockDim.x) {
+    const double v = norms[r];
+    if (isfinite(v)) sn += v;
+    else nf += 1.0;
+    if (have_energy) se += energy[r];
+  }
+  sn = wave_sum(sn);
+  se = wave_sum(se);
+  nf = wave_sum(nf);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sn;
+    red[1][threadIdx.x >> 6] = se;
+    red[2][threadIdx.x >> 6] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tn = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double te = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double tf = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    out[0] = qsum[0];
+    out[1] = qsum[0] - vacuum;
+    out[2] = have_cl ? qsum[1] : 0.0;
+    out[3] = have_cl ? qsum[2] : 0.0;
+    out[4] = have_energy ? te / (double)n_real : 0.0;
+    out[5] = (n_real - tf) > 0 ? tn / (double)(n_real - tf) : 0.0;
+    out[6] = tf;
+    out[7] = (have_energy && have_cl) ? energy[n_real] : 0.0;
+  }
+}
+
+hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
+                          const double* energy_dev, hipStream_t s) {
+  const int64_t nwaves = (P.ncell + 63) / 64;
+  MomArgs a;
+  a.psi = psi;
+  a.psi_cl = psi_cl;
+  a.n_real = P.p.n_real;
+  a.ncell = P.ncell;
+  a.m_tot = P.p.m_tot;
+  a.dV = P.dV;
+  a.mean_psi = reinterpret_cast<cx<double>*>(out->mean_psi);
+  a.mean_abs2 = out->mean_abs2;
+  a.mean_rho = out->mean_rho;
+  a.var_rho = out->var_rho;
+  a.wave_norm = P.partial;
+  a.wave_q = P.partial + P.p.n_real * nwaves;
+  a.nwaves = nwaves;
+  double* norms = a.wave_q + 3 * nwaves;  // [n_real]
+  double* qsum = norms + P.p.n_real;      // [3]
+  dim3 grid((unsigned)((P.ncell + 255) / 256));
+  if (P.fp32) hipLaunchKernelGGL(moments_cell_kernel<float>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(moments_cell_kernel<double>, grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(row_sum_kernel, dim3((unsigned)P.p.n_real), dim3(256), 0, s, a.wave_norm, nwaves, P.dV, norms);
+  hipLaunchKernelGGL(row_sum_kernel, dim3(3), dim3(256), 0, s, a.wave_q, nwaves, 1.0, qsum);
+  if (out->norm)
+    hipMemcpyAsync(out->norm, norms, sizeof(double) * P.p.n_real, hipMemcpyDeviceToDevice, s);
+  if (out->scalars) {
+    const double vacuum = (double)P.ncell / (2.0 * P.p.n_tot);
+    hipLaunchKernelGGL(scalars_kernel, dim3(1), dim3(256), 0, s, qsum, norms, energy_dev, (int64_t)P.p.n_real, vacuum,
+                       psi_cl ? 1 : 0, energy_dev ? 1 : 0, out->scalars);
+  }
+  return hipGetLastError();
+}
+
+// Energy assembly: E_f = m_tot [ (hbar^2/2) dV sum_a KS_a / n_a + (1/2) dV PS ]
+// with KS_a the per-axis sums sum k_a^2 |FFT_a psi|^2 over pencils and PS = sum V |psi|^2.
+__global__ void __launch_bounds__(256) energy_kernel(const double* __restrict__ partial, int64_t gstride,
+                                                     int64_t nfield, int ng0, int ng1, int ng2, int ngp, int dim,
+                                                     int n0, int n1, int n2, double hbar, double m_tot, double dV,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4];
+  const int64_t f = blockIdx.x;
+  const int ng[4] = {ng0, ng1, ng2, ngp};
+  const int nn[3] = {n0, n1, n2};
+  double total = 0.0;
+  for (int slot = 0; slot < 4; ++slot) {
+    if (slot < 3 && slot >= dim) continue;
+    const double* src = partial + (int64_t)slot * gstride + f * ng[slot];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ng[slot]; i += blockDim.x) s += src[i];
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    const double t = red[0] + red[1] + red[2] + red[3];
+    if (slot < 3) total += 0.5 * hbar * hbar * dV * t / (double)nn[slot];
+    else total += 0.5 * dV * t;
+  }
+  if (threadIdx.x == 0) out[f] = m_tot * total;
+}
+
+hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t gstride, int64_t nfield,
+                                  const int ng[4], double* out, hipStream_t s) {
+  if (nfield <= 0) return hipSuccess;
+  hipLaunchKernelGGL(energy_kernel, dim3((unsigned)nfield), dim3(256), 0, s, partial, gstride, nfield, ng[0], ng[1],
+                     ng[2], ng[3], P.dim, P.n[0], P.n[1], P.n[2], P.p.hbar_m, P.p.m_tot, P.dV, out);
+  return hipGetLastError();
+}
+
+}  // namespace tw

@@ -1,0 +1,422 @@
+// Split-step kernels: per-axis pencil passes for D >= 2, a resident whole-run
+// kernel for D = 1, drift phase tables and per-field density means.
+//
+// The step (Sec. "Integrating the equations of motion"): drift, potential from
+// the drifted field's density, kick, drift. The kinetic propagator is
+// separable, exp(-i hbar |k|^2 tau/2) = prod_d exp(-i hbar k_d^2 tau/2), so a
+// D-dim drift is a product of 1D drifts along each axis, each done as
+// FFT -> pointwise factor -> inverse FFT inside one pass with the pencil held
+// in registers/LDS. The Poisson solve (V_k = -4 pi G rho_k/|k|^2, V_0 = 0) is
+// not separable and needs the full D-dim transform of rho; two realizations
+// share one complex transform (z = rho_A + i rho_B; the Green's function is
+// real and even, so V_A = Re, V_B = Im of the inverse).
+#include "common.hpp"
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace tw {
+
+template <class T, int N>
+__host__ __device__ constexpr int pencils_per_group() {
+  constexpr int TPP = fft_threads(N);
+  int c = 256 / TPP;
+  const int coal = (sizeof(T) == 8) ? 8 : 16;  // >= 128 contiguous bytes on strided axes
+  if (c < coal) c = coal;
+  while (c > 1 && c * TPP > 1024) c /= 2;
+  while (c > 1 && (long)c * N * 2 * (long)sizeof(T) > 65536) c /= 2;
+  return c;
+}
+
+template <class T>
+__device__ __forceinline__ cx<T>* field_ptr(const PassArgs& a, int64_t f) {
+  return f < a.n_real ? reinterpret_cast<cx<T>*>(a.psi) + f * a.ncell : reinterpret_cast<cx<T>*>(a.psi_cl);
+}
+
+// Sum of `x` over the workgroup; result valid in thread 0. `red` holds one
+// double per wave.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += red[w];
+  }
+  return s;
+}
+
+template <class T, int N, int MODE>
+__global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) pass_kernel(PassArgs a) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int R = N / TPP;
+  constexpr int C = pencils_per_group<T, N>();
+  __shared__ cx<T> lds_all[C * N];
+  __shared__ double red[16];
+
+  const int tid = threadIdx.x;
+  const bool rows = (a.stride == 1);
+  const int c = rows ? tid / TPP : tid % C;
+  const int t = rows ? tid % TPP : tid / C;
+  cx<T>* lds = lds_all + c * N;
+  const int64_t npencils = a.ncell / N;
+  const int64_t p = (int64_t)blockIdx.x * C + c;
+  const bool active = p < npencils;
+  const int64_t pp = active ? p : 0;
+  const int64_t base = (pp % a.stride) + (pp / a.stride) * a.stride * N;
+  const int64_t stride = a.stride;
+  const int64_t pair = blockIdx.y;
+  const cx<T>* __restrict__ twd = reinterpret_cast<const cx<T>*>(a.twd);
+
+  auto load = [&](const cx<T>* f, cx<T> (&v)[R]) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = active ? f[base + (int64_t)(t + TPP * m) * stride] : cx<T>{(T)0, (T)0};
+  };
+  auto store = [&](cx<T>* f, const cx<T> (&v)[R]) {
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) f[base + (int64_t)(t + TPP * m) * stride] = v[m];
+    }
+  };
+  auto drift = [&](cx<T> (&v)[R]) {
+    fft_pencil<T, N, false>(v, lds, t, twd);
+    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
+    fft_pencil<T, N, true>(v, lds, t, twd);
+  };
+
+  if constexpr (MODE == PASS_DRIFT) {
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = 2 * pair + k;
+      if (f >= a.nfield) break;
+      cx<T>* fp = field_ptr<T>(a, f);
+      cx<T> v[R];
+      load(fp, v);
+      drift(v);
+      store(fp, v);
+    }
+  } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
+    double rho[2][R];
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = 2 * pair + k;
+      if (f < a.nfield) {
+        cx<T>* fp = field_ptr<T>(a, f);
+        cx<T> v[R];
+        load(fp, v);
+        if constexpr (MODE == PASS_DRIFT_RHO) {
+          drift(v);
+          store(fp, v);
+        }
+        const double mean = a.rho_mean ? a.rho_mean[f] : 0.0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) rho[k][m] = a.m_tot * (double)abs2(v[m]) - mean;
+      } else {
+#pragma unroll
+        for (int m = 0; m < R; ++m) rho[k][m] = 0.0;
+      }
+    }
+    cx<T> zv[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) zv[m] = {(T)rho[0][m], (T)rho[1][m]};
+    fft_pencil<T, N, false>(zv, lds, t, twd);
+    store(reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell, zv);
+  } else if constexpr (MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON) {
+    cx<T>* zp = reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell;
+    cx<T> zv[R];
+    load(zp, zv);
+    if constexpr (MODE == PASS_ZINV) {
+      fft_pencil<T, N, true>(zv, lds, t, twd);
+    } else {
+      fft_pencil<T, N, false>(zv, lds, t, twd);
+    }
+    if constexpr (MODE == PASS_ZPOISSON) {
+      const int64_t x0 = base % a.n[0];
+      const int64_t y0 = (base / a.n[0]) % a.n[1];
+      const int64_t z0 = base / ((int64_t)a.n[0] * a.n[1]);
+      const int64_t co[3] = {x0, y0, z0};
+      double k2o = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (d != a.axis) k2o += a.k2[d][co[d]];
+      const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double k2 = k2o + k2a[t + TPP * m];
+        const double g = (k2 == 0.0) ? 0.0 : a.green / k2;
+        zv[m] = mul_d(zv[m], g);
+      }
+      fft_pencil<T, N, true>(zv, lds, t, twd);
+    }
+    store(zp, zv);
+  } else if constexpr (MODE == PASS_KICK_DRIFT) {
+    cx<T> zv[R];
+    load(reinterpret_cast<const cx<T>*>(a.z) + pair * a.ncell, zv);
+    fft_pencil<T, N, true>(zv, lds, t, twd);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = 2 * pair + k;
+      if (f >= a.nfield) break;
+      cx<T>* fp = field_ptr<T>(a, f);
+      cx<T> v[R];
+      load(fp, v);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double V = (double)(k == 0 ? zv[m].re : zv[m].im);
+        v[m] = cmul(v[m], expmi<T>(a.kick * V));
+      }
+      drift(v);
+      store(fp, v);
+    }
+  } else if constexpr (MODE == PASS_KIN_SUM) {
+    const double* __restrict__ k2a = a.k2[a.axis];
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = 2 * pair + k;
+      if (f >= a.nfield) break;
+      cx<T> v[R];
+      load(field_ptr<T>(a, f), v);
+      fft_pencil<T, N, false>(v, lds, t, twd);
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) s += k2a[t + TPP * m] * (double)abs2(v[m]);
+      s = block_sum(s, red);
+      if (tid == 0) a.partial[f * gridDim.x + blockIdx.x] = s;
+    }
+  } else if constexpr (MODE == PASS_POT_SUM) {
+    cx<T> zv[R];
+    load(reinterpret_cast<const cx<T>*>(a.z) + pair * a.ncell, zv);
+    if (a.pot_green) {
+      const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double k2 = k2a[t + TPP * m];
+        zv[m] = mul_d(zv[m], (k2 == 0.0) ? 0.0 : a.green / k2);
+      }
+    }
+    fft_pencil<T, N, true>(zv, lds, t, twd);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = 2 * pair + k;
+      if (f >= a.nfield) break;
+      cx<T> v[R];
+      load(field_ptr<T>(a, f), v);
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) s += (double)(k == 0 ? zv[m].re : zv[m].im) * (double)abs2(v[m]);
+      s = block_sum(s, red);
+      if (tid == 0) a.partial[f * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+template <class T, int N>
+static hipError_t launch_pass_tn(int mode, const PassArgs& a, hipStream_t s, int ny) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int C = pencils_per_group<T, N>();
+  const int64_t npencils = a.ncell / N;
+  dim3 grid((unsigned)((npencils + C - 1) / C), (unsigned)ny);
+  dim3 block(C * TPP);
+  switch (mode) {
+    case PASS_DRIFT: hipLaunchKernelGGL((pass_kernel<T, N, PASS_DRIFT>), grid, block, 0, s, a); break;
+    case PASS_DRIFT_RHO: hipLaunchKernelGGL((pass_kernel<T, N, PASS_DRIFT_RHO>), grid, block, 0, s, a); break;
+    case PASS_ZFWD: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZFWD>), grid, block, 0, s, a); break;
+    case PASS_ZPOISSON: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZPOISSON>), grid, block, 0, s, a); break;
+    case PASS_ZINV: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZINV>), grid, block, 0, s, a); break;
+    case PASS_KICK_DRIFT: hipLaunchKernelGGL((pass_kernel<T, N, PASS_KICK_DRIFT>), grid, block, 0, s, a); break;
+    case PASS_RHO: hipLaunchKernelGGL((pass_kernel<T, N, PASS_RHO>), grid, block, 0, s, a); break;
+    case PASS_KIN_SUM: hipLaunchKernelGGL((pass_kernel<T, N, PASS_KIN_SUM>), grid, block, 0, s, a); break;
+    case PASS_POT_SUM: hipLaunchKernelGGL((pass_kernel<T, N, PASS_POT_SUM>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_pass_t(int mode, const PassArgs& a, hipStream_t s, int ny) {
+  switch (a.n[a.axis]) {
+    case 16: return launch_pass_tn<T, 16>(mode, a, s, ny);
+    case 32: return launch_pass_tn<T, 32>(mode, a, s, ny);
+    case 64: return launch_pass_tn<T, 64>(mode, a, s, ny);
+    case 128: return launch_pass_tn<T, 128>(mode, a, s, ny);
+    case 256: return launch_pass_tn<T, 256>(mode, a, s, ny);
+    case 512: return launch_pass_tn<T, 512>(mode, a, s, ny);
+    case 1024: return launch_pass_tn<T, 1024>(mode, a, s, ny);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool pass_length_supported(int n) {
+  return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+}
+
+int pass_pencils_per_group(int n, bool fp32) {
+  auto pick = [&](auto tag) -> int {
+    using T = decltype(tag);
+    switch (n) {
+      case 16: return pencils_per_group<T, 16>();
+      case 32: return pencils_per_group<T, 32>();
+      case 64: return pencils_per_group<T, 64>();
+      case 128: return pencils_per_group<T, 128>();
+      case 256: return pencils_per_group<T, 256>();
+      case 512: return pencils_per_group<T, 512>();
+      case 1024: return pencils_per_group<T, 1024>();
+      default: return 0;
+    }
+  };
+  return fp32 ? pick(float{}) : pick(double{});
+}
+
+hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int ny) {
+  if (ny <= 0) return hipSuccess;
+  return P.fp32 ? launch_pass_t<float>(mode, a, s, ny) : launch_pass_t<double>(mode, a, s, ny);
+}
+
+// ------------------------------------------------------------------ 1D resident
+// D = 1: a whole field fits in one workgroup's registers and LDS, so all steps
+// run inside one launch with no HBM traffic between steps. Each field is
+// transformed on its own (complex transform of the real density).
+template <class T, int N>
+__host__ __device__ constexpr int fields_per_group_1d() {
+  constexpr int TPP = fft_threads(N);
+  return TPP >= 64 ? 1 : 64 / TPP;
+}
+
+template <class T, int N>
+__global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))) step1d_kernel(void* psi, void* psi_cl, int64_t n_real, int64_t nfield,
+                                                       int64_t nsteps, const cx<T>* __restrict__ twd,
+                                                       const double* __restrict__ k2,
+                                                       const cx<double>* __restrict__ ph_half,
+                                                       const cx<double>* __restrict__ ph_full, double green,
+                                                       double kick, double m_tot,
+                                                       const double* __restrict__ rho_mean) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int R = N / TPP;
+  constexpr int C = fields_per_group_1d<T, N>();
+  __shared__ cx<T> lds_all[C * N];
+  const int c = threadIdx.x / TPP;
+  const int t = threadIdx.x % TPP;
+  cx<T>* lds = lds_all + c * N;
+  const int64_t f = (int64_t)blockIdx.x * C + c;
+  const bool active = f < nfield;
+  cx<T>* fp = !active ? nullptr
+              : (f < n_real ? reinterpret_cast<cx<T>*>(psi) + f * N : reinterpret_cast<cx<T>*>(psi_cl));
+  const double mean = (active && rho_mean) ? rho_mean[f] : 0.0;
+
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = active ? fp[t + TPP * m] : cx<T>{(T)0, (T)0};
+  double g[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const double kk = k2[t + TPP * m];
+    g[m] = (kk == 0.0) ? 0.0 : green / kk;
+  }
+  auto drift = [&](const cx<double>* ph) {
+    fft_pencil<T, N, false>(v, lds, t, twd);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
+    fft_pencil<T, N, true>(v, lds, t, twd);
+  };
+
+  drift(ph_half);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    cx<T> zv[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) zv[m] = {(T)(m_tot * (double)abs2(v[m]) - mean), (T)0};
+    fft_pencil<T, N, false>(zv, lds, t, twd);
+#pragma unroll
+    for (int m = 0; m < R; ++m) zv[m] = mul_d(zv[m], g[m]);
+    fft_pencil<T, N, true>(zv, lds, t, twd);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], expmi<T>(kick * (double)zv[m].re));
+    drift(s + 1 < nsteps ? ph_full : ph_half);
+  }
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) fp[t + TPP * m] = v[m];
+  }
+}
+
+template <class T, int N>
+static hipError_t launch_step1d_tn(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
+                                   const void* ph_half, const void* ph_full, double kick, hipStream_t s) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int C = fields_per_group_1d<T, N>();
+  dim3 grid((unsigned)((nfield + C - 1) / C)), block(C * TPP);
+  const double green = -4.0 * M_PI * P.p.G / (double)N;
+  hipLaunchKernelGGL((step1d_kernel<T, N>), grid, block, 0, s, psi, psi_cl, (int64_t)P.p.n_real, nfield, nsteps,
+                     reinterpret_cast<const cx<T>*>(P.twd[0]), P.k2[0],
+                     reinterpret_cast<const cx<double>*>(ph_half), reinterpret_cast<const cx<double>*>(ph_full),
+                     green, kick, P.p.m_tot, P.fp32 ? P.rho_mean : nullptr);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_step1d_t(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
+                                  const void* ph_half, const void* ph_full, double kick, hipStream_t s) {
+  switch (P.n[0]) {
+    case 8: return launch_step1d_tn<T, 8>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 16: return launch_step1d_tn<T, 16>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 32: return launch_step1d_tn<T, 32>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 64: return launch_step1d_tn<T, 64>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 128: return launch_step1d_tn<T, 128>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 256: return launch_step1d_tn<T, 256>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 512: return launch_step1d_tn<T, 512>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    case 1024: return launch_step1d_tn<T, 1024>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool step1d_length_supported(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+
+hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
+                         const void* ph_half, const void* ph_full, double kick, hipStream_t s) {
+  return P.fp32 ? launch_step1d_t<float>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s)
+                : launch_step1d_t<double>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+}
+
+// ---------------------------------------------------------------- tables
+// out[j] = exp(-i hbar k_j^2 tau / 2) / n  (FP64), k_j^2 from the axis table.
+__global__ void phase_table_kernel(cx<double>* out, const double* __restrict__ k2, int n, double hbar, double tau) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double arg = hbar * k2[j] * tau * 0.5;
+  double s, c;
+  sincos(arg, &s, &c);
+  const double inv = 1.0 / (double)n;
+  out[j] = {c * inv, -s * inv};
+}
+
+hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hipStream_t s) {
+  const int n = P.n[axis];
+  hipLaunchKernelGGL(phase_table_kernel, dim3((n + 255) / 256), dim3(256), 0, s, reinterpret_cast<cx<double>*>(out),
+                     P.k2[axis], n, P.p.hbar_m, tau);
+  return hipGetLastError();
+}
+
+// mean density m_tot * sum_g |psi_g|^2 / N of every field, FP64.
+template <class T>
+__global__ void __launch_bounds__(256) field_mean_kernel(const void* psi, const void* psi_cl, int64_t n_real,
+                                                         int64_t ncell, double m_tot, double* out) {
+  __shared__ double red[4];
+  const int64_t f = blockIdx.x;
+  const cx<T>* fp = f < n_real ? reinterpret_cast<const cx<T>*>(psi) + f * ncell : reinterpret_cast<const cx<T>*>(psi_cl);
+  double s = 0.0;
+  for (int64_t g = threadIdx.x; g < ncell; g += blockDim.x) s += (double)abs2(fp[g]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[f] = m_tot * s / (double)ncell;
+}
+
+hipError_t launch_field_mean(const Plan& P, const void* psi, const void* psi_cl, int64_t nfield, double* out,
+                             hipStream_t s) {
+  if (nfield <= 0) return hipSuccess;
+  if (P.fp32)
+    hipLaunchKernelGGL(field_mean_kernel<float>, dim3((unsigned)nfield), dim3(256), 0, s, psi, psi_cl,
+                       (int64_t)P.p.n_real, P.ncell, P.p.m_tot, out);
+  else
+    hipLaunchKernelGGL(field_mean_kernel<double>, dim3((unsigned)nfield), dim3(256), 0, s, psi, psi_cl,
+                       (int64_t)P.p.n_real, P.ncell, P.p.m_tot, out);
+  return hipGetLastError();
+}
+
+}  // namespace tw

@@ -1,0 +1,226 @@
+"""ctypes binding of the C ABI in include/tw.h (argument marshalling only).
+
+Every computation happens in the HIP library ``libtw.so``; this module only
+converts torch device tensors to pointers, passes the current HIP stream and
+raises on a non-zero status. There is no CPU fallback: importing works without
+the library, but creating a Plan raises if it is missing.
+"""
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_LIB = None
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtw.so")
+
+TW_FP64 = 0
+TW_FP32_SPLIT = 1
+STATUS = {0: "TW_OK", -1: "TW_EINVAL", -2: "TW_EUNSUPPORTED", -3: "TW_ELAYOUT", -4: "TW_EHIP", -5: "TW_ENOMEM"}
+SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "norm_mean",
+                "nonfinite", "energy_classical")
+
+# Exported entry points and their argument types (mirrors include/tw.h).
+EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_moments",
+           "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
+NUM_KERNEL_KINDS = 16
+
+
+class TwProblem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
+                ("hbar_m", ctypes.c_double), ("G", ctypes.c_double), ("m_tot", ctypes.c_double),
+                ("n_tot", ctypes.c_double), ("n_real", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class TwMomentsOut(ctypes.Structure):
+    _fields_ = [("mean_psi", ctypes.c_void_p), ("mean_abs2", ctypes.c_void_p), ("mean_rho", ctypes.c_void_p),
+                ("var_rho", ctypes.c_void_p), ("norm", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("scalars", ctypes.c_void_p)]
+
+
+class TwError(RuntimeError):
+    pass
+
+
+def load_library(path=LIB_PATH):
+    """Load libtw.so (built by paper_2310_07119_amd.build). Raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise TwError(f"HIP library not built: {path} is missing (run `python -m paper_2310_07119_amd.build`)")
+    lib = ctypes.CDLL(path)
+    vp, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.tw_plan_create.argtypes = [ctypes.POINTER(TwProblem), ctypes.POINTER(vp)]
+    lib.tw_plan_destroy.argtypes = [vp]
+    lib.tw_sample.argtypes = [vp, vp, u64, i64, vp, vp]
+    lib.tw_step.argtypes = [vp, vp, vp, i64, dbl, vp]
+    lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
+    lib.tw_plan_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.tw_plan_get_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.tw_kernel_kind_name.argtypes = [ctypes.c_int32]
+    lib.tw_kernel_kind_name.restype = ctypes.c_char_p
+    lib.tw_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("tw_last_error", "tw_kernel_kind_name"):
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = _LIB.tw_last_error().decode()
+        raise TwError(f"{what} failed: {STATUS.get(rc, rc)}: {msg}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class Problem:
+    """Problem statement of Eq. (mft_normed) on a periodic grid (x first)."""
+    n: tuple
+    box: tuple = None
+    hbar_m: float = 1.0
+    G: float = 1.0
+    m_tot: float = 1.0
+    n_tot: float = 1e4
+    n_real: int = 64
+    precision: str = "fp64"      # "fp64" or "fp32"
+    extra: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        self.n = tuple(int(v) for v in self.n)
+        if self.box is None:
+            self.box = (1.0,) * len(self.n)
+        self.box = tuple(float(v) for v in self.box)
+
+    @property
+    def dim(self):
+        return len(self.n)
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    @property
+    def ncell(self):
+        return int(math.prod(self.n))
+
+    @property
+    def dV(self):
+        dv = 1.0
+        for d in range(self.dim):
+            dv = dv * (self.box[d] / self.n[d])
+        return dv
+
+    @property
+    def cdtype(self):
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+
+class Plan:
+    """Owns a tw_plan (tables + device workspace) for one Problem on the current device."""
+
+    def __init__(self, problem: Problem):
+        lib = load_library()
+        self.problem = problem
+        pr = TwProblem()
+        pr.dim = problem.dim
+        for d in range(3):
+            pr.n[d] = problem.n[d] if d < problem.dim else 1
+            pr.box[d] = problem.box[d] if d < problem.dim else 1.0
+        pr.hbar_m, pr.G, pr.m_tot, pr.n_tot = problem.hbar_m, problem.G, problem.m_tot, problem.n_tot
+        pr.n_real = problem.n_real
+        pr.precision = TW_FP64 if problem.precision == "fp64" else TW_FP32_SPLIT
+        pr.reserved = 0
+        h = ctypes.c_void_p()
+        _check(lib.tw_plan_create(ctypes.byref(pr), ctypes.byref(h)), "tw_plan_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tw_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- calls
+    def empty_ensemble(self, device="cuda"):
+        p = self.problem
+        return torch.empty((p.n_real,) + p.shape, dtype=p.cdtype, device=device)
+
+    def sample(self, psi_cl, seed, real_offset=0, out=None):
+        """Draw the ensemble (tw_sample). psi_cl: complex128 device tensor of the grid shape."""
+        assert psi_cl.dtype == torch.complex128 and psi_cl.is_cuda and psi_cl.is_contiguous()
+        out = self.empty_ensemble(psi_cl.device) if out is None else out
+        assert out.dtype == self.problem.cdtype and out.is_contiguous()
+        _check(self._lib.tw_sample(self._h, _ptr(psi_cl), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                   int(real_offset), _ptr(out), _stream()), "tw_sample")
+        return out
+
+    def step(self, psi, nsteps, dt, psi_classical=None):
+        """Advance psi (and psi_classical) in place by nsteps leapfrog steps (tw_step)."""
+        assert psi.dtype == self.problem.cdtype and psi.is_contiguous()
+        if psi_classical is not None:
+            assert psi_classical.dtype == self.problem.cdtype and psi_classical.is_contiguous()
+        _check(self._lib.tw_step(self._h, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
+               "tw_step")
+        return psi
+
+    def set_profiling(self, enable=True):
+        """Bracket every kernel launch with HIP events on its stream (tw_plan_set_profiling)."""
+        _check(self._lib.tw_plan_set_profiling(self._h, 1 if enable else 0), "tw_plan_set_profiling")
+
+    def profile(self):
+        """{kernel kind: (launches, total device ms)} since the last call (tw_plan_get_profile)."""
+        n = NUM_KERNEL_KINDS
+        launches = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        _check(self._lib.tw_plan_get_profile(self._h, n, launches, ms), "tw_plan_get_profile")
+        out = {}
+        for k in range(n):
+            if launches[k]:
+                out[self._lib.tw_kernel_kind_name(k).decode()] = (int(launches[k]), float(ms[k]))
+        return out
+
+    def moments(self, psi, psi_classical=None, energy=True, per_cell=True):
+        """Ensemble moments (tw_moments) as a dict of device tensors (scalars on the host)."""
+        p = self.problem
+        dev = psi.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = {}
+        if per_cell:
+            out["mean_psi"] = torch.empty(p.shape, dtype=torch.complex128, device=dev)
+            for k in ("mean_abs2", "mean_rho", "var_rho"):
+                out[k] = torch.empty(p.shape, **f64)
+        out["norm"] = torch.empty(p.n_real, **f64)
+        if energy:
+            out["energy"] = torch.empty(p.n_real, **f64)
+        scal = torch.empty(8, **f64)
+        mo = TwMomentsOut()
+        for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "norm", "energy"):
+            setattr(mo, k, out[k].data_ptr() if k in out else None)
+        mo.scalars = scal.data_ptr()
+        _check(self._lib.tw_moments(self._h, _ptr(psi), _ptr(psi_classical), ctypes.byref(mo), _stream()),
+               "tw_moments")
+        vals = scal.cpu().tolist()
+        for name, v in zip(SCALAR_NAMES, vals):
+            out[name] = v
+        out["nonfinite"] = int(out["nonfinite"])
+        return out

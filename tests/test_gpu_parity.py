@@ -1,0 +1,88 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs. Bars: sampled states bit-exact; FP64 results within
+1e-10 and FP32-split results within 1e-4 normwise relative error."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import twa_oracle as tw
+from paper_2310_07119_amd import Problem, inputs
+from tests.gpu_util import TOL, gpu_run, oracle_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (n, n_real, nsteps, dt, hbar, G, m_tot, n_tot)
+    ((256,), 64, 40, 1e-4, 1.0, 1.0, 1.0, 1e4),            # 1D workload shape, fewer steps
+    ((16,), 3, 25, 1e-3, 0.3, 2.0, 5.0, 50.0),              # 1D tiny, odd ensemble
+    ((64, 32), 5, 12, 2e-4, 1.0, 1.0, 30.0, 1e5),           # 2D, several tiles, odd ensemble
+    ((32, 128), 2, 10, 2e-4, 0.5, 3.0, 10.0, 1e5),          # 2D, long y axis
+    ((16, 16, 32), 3, 6, 2e-4, 1.0, 1.0, 20.0, 1e6),        # 3D
+    ((32, 16, 16), 4, 5, 1e-4, 1.0, 2.0, 10.0, 1e6),        # 3D, x longest
+]
+
+
+def _ids(c):
+    return "x".join(map(str, c[0])) + f"_r{c[1]}"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_sample_step_moments_vs_oracle(case, precision):
+    n, nr, nsteps, dt, hbar, G, m_tot, n_tot = case
+    p = Problem(n=n, hbar_m=hbar, G=G, m_tot=m_tot, n_tot=n_tot, n_real=nr, precision=precision)
+    psi_cl = inputs.lognormal_field(n, p.box, kcut=min(n) // 4, seed=1)
+    seed = 1234567
+    print(f"case n={n} n_real={nr} {precision}", flush=True)
+    g = gpu_run(p, psi_cl, seed, nsteps, dt, real_offset=7)
+    prob = oracle_problem(p)
+    psi0 = tw.sample(prob.grid, psi_cl, nr, n_tot, seed, real_offset=7)
+    # sampled initial state: bit-exact (FP32 = the FP64 draw rounded to nearest)
+    if precision == "fp64":
+        assert np.array_equal(g["psi0"], psi0)
+    else:
+        assert np.array_equal(g["psi0"], psi0.astype(np.complex64))
+        psi0 = g["psi0"].astype(np.complex128)      # oracle continues from the stored FP32 state
+    psi = tw.evolve(prob, psi0, nsteps, dt)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64).astype(np.complex128)
+    cl = tw.evolve(prob, cl0, nsteps, dt)
+    tol = TOL[precision]
+    assert rel(g["psi"], psi) < tol
+    assert rel(g["cl"], cl) < tol
+    ref = tw.moments(prob, psi, n_tot, cl)
+    m = g["mom"]
+    for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "norm", "energy"):
+        assert rel(m[k], ref[k]) < tol * 10, k
+    for k in ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2"):
+        assert abs(m[k] - ref[k]) <= tol * 10 * max(abs(ref[k]), 1e-300) + 1e-300, k
+    assert abs(m["energy_mean"] - ref["energy"].mean()) < tol * 10 * abs(ref["energy"].mean())
+    assert abs(m["energy_classical"] - tw.energy(prob, cl)) < tol * 10 * abs(tw.energy(prob, cl))
+    assert m["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_steps_and_no_classical(precision):
+    p = Problem(n=(32, 32), n_real=3, n_tot=1e3, precision=precision)
+    psi_cl = inputs.lognormal_field(p.n, p.box, seed=2)
+    g = gpu_run(p, psi_cl, 5, 0, 1e-3, with_classical=False)
+    assert np.array_equal(g["psi"], g["psi0"])
+    prob = oracle_problem(p)
+    ref = tw.moments(prob, g["psi0"].astype(np.complex128), p.n_tot)
+    assert abs(g["mom"]["Q_raw"] - ref["Q_raw"]) < 1e-10 * ref["Q_raw"]
+    assert g["mom"]["dev_rho_L1"] == 0.0
+
+
+def test_nonfinite_realization_is_counted():
+    p = Problem(n=(32, 16), n_real=4, n_tot=1e3)
+    from paper_2310_07119_amd import Plan
+    plan = Plan(p)
+    psi = torch.ones((4, 16, 32), dtype=torch.complex128, device="cuda")
+    psi[2, 3, 4] = float("nan")
+    m = plan.moments(psi, energy=False)
+    assert m["nonfinite"] == 1
