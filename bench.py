@@ -85,7 +85,7 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     elapsed = t1 - t0
     work = p.n_real * p.ncell * steps
     res = dict(value=work / elapsed, ms_per_step=1e3 * elapsed / steps, elapsed_s=elapsed, prof=prof,
-               mom={k: (v.double().cpu() if torch.is_tensor(v) else v) for k, v in mom.items()},
+               mom={k: (v.cpu() if torch.is_tensor(v) else v) for k, v in mom.items()},
                problem=p)
     # dominant kernel
     elem = 16 if precision == "fp64" else 8

@@ -113,7 +113,7 @@ int check_ptr(const Plan& P, const void* p, const char* name, bool nullable) {
 
 // groups (workgroups along x) of a pass along `axis`
 int pass_groups(const Plan& P, int axis) {
-  const int c = pass_pencils_per_group(P.n[axis], P.fp32);
+  const int c = pass_pencils_per_group(P.n[axis], P.fp32, axis == 0);
   const int64_t np = P.ncell / P.n[axis];
   return (int)((np + c - 1) / c);
 }

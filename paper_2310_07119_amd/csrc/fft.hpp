@@ -14,6 +14,14 @@
 //
 // Forward: X_k = sum_n x_n exp(-2 pi i k n / N). Inverse: conjugate twiddles,
 // no 1/N (callers fold normalisation into their pointwise factors).
+//
+// LDS: element i of a pencil lives at lds_pad(i) = i + i/8, and consecutive
+// pencils are fft_lds_stride(N) = N + N/8 + 1 elements apart. The first
+// stage writes with a stride of R = 8 elements; the padding turns it into an
+// odd stride so the lanes of one LDS cycle hit distinct banks.
+//
+// SYNC_WAVE: every pencil is owned by the lanes of a single wavefront, so the
+// exchanges only need wavefront-level ordering; otherwise a workgroup barrier.
 #pragma once
 #include "common.hpp"
 #include <utility>
@@ -21,23 +29,28 @@
 namespace tw {
 
 // ---------------------------------------------------------------- plans
-// Power-of-two lengths use radix R = 8 points per thread (fewer threads for N < 8).
-__host__ __device__ constexpr int fft_points_per_thread(int N) { return N >= 8 ? 8 : N; }
+// Power-of-two lengths: 8 points per thread (N <= 512, at most 64 threads per
+// pencil), 16 for N = 1024 (so a pencil never spans two wavefronts); radix-8
+// stages and one smaller last stage.
+__host__ __device__ constexpr int fft_points_per_thread(int N) { return N > 512 ? 16 : (N >= 8 ? 8 : N); }
 __host__ __device__ constexpr int fft_threads(int N) { return N / fft_points_per_thread(N); }
+__host__ __device__ constexpr int fft_lds_stride(int N) { return N + N / 8 + 1; }
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 3); }
 
+__host__ __device__ constexpr int fft_next_radix(int rem) { return (rem % 8 == 0) ? 8 : rem; }
 __host__ __device__ constexpr int fft_num_stages(int N, int R) {
   int s = 0;
   int rem = N;
   while (rem > 1) {
-    rem /= (rem % R == 0) ? R : rem;
+    rem /= fft_next_radix(rem);
     ++s;
   }
   return s;
 }
 __host__ __device__ constexpr int fft_stage_radix(int N, int R, int stage) {
   int rem = N;
-  for (int s = 0; s < stage; ++s) rem /= (rem % R == 0) ? R : rem;
-  return (rem % R == 0) ? R : rem;
+  for (int s = 0; s < stage; ++s) rem /= fft_next_radix(rem);
+  return fft_next_radix(rem);
 }
 __host__ __device__ constexpr int fft_stage_ns(int N, int R, int stage) {
   int ns = 1;
@@ -113,7 +126,18 @@ struct Butterfly<T, 8, INV> {
 };
 
 // ---------------------------------------------------------------- stages
-template <class T, int N, int TPP, bool INV, int S>
+template <bool SYNC_WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (SYNC_WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <class T, int N, int TPP, bool INV, bool SW, int S>
 struct FftStage {
   static constexpr int R = N / TPP;
   static constexpr int NS = fft_num_stages(N, R);
@@ -124,12 +148,12 @@ struct FftStage {
 
   static __device__ __forceinline__ void run(cx<T> (&v)[R], cx<T>* lds, int t, const cx<T>* __restrict__ twd) {
     if constexpr (S > 0) {
-      __syncthreads();  // previous stage's LDS writes are visible
+      fft_sync<SW>();  // previous stage's LDS writes are visible
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + TPP * i;
 #pragma unroll
-        for (int r = 0; r < RS; ++r) v[i + r * NB] = lds[j + r * (N / RS)];
+        for (int r = 0; r < RS; ++r) v[i + r * NB] = lds[lds_pad(j + r * (N / RS))];
       }
     }
 #pragma unroll
@@ -146,26 +170,27 @@ struct FftStage {
       Butterfly<T, RS, INV>::run(v, i, NB);
     }
     if constexpr (S < NS - 1) {
-      __syncthreads();  // every thread has consumed the previous contents
+      fft_sync<SW>();  // every lane has consumed the previous contents
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + TPP * i;
         const int base = (j / NSB) * NSB * RS + (j % NSB);
 #pragma unroll
-        for (int r = 0; r < RS; ++r) lds[base + r * NSB] = v[i + r * NB];
+        for (int r = 0; r < RS; ++r) lds[lds_pad(base + r * NSB)] = v[i + r * NB];
       }
-      FftStage<T, N, TPP, INV, S + 1>::run(v, lds, t, twd);
+      FftStage<T, N, TPP, INV, SW, S + 1>::run(v, lds, t, twd);
     }
   }
 };
 
 // Transform the pencil held in v (natural layout) in place. `lds` is this
-// pencil's private N-element buffer; every thread of the workgroup must call
-// with the same N (the stage barriers are workgroup-wide). twd[e] = W_N^e.
-template <class T, int N, bool INV>
+// pencil's private buffer of fft_lds_stride(N) elements. With SYNC_WAVE =
+// false every thread of the workgroup must make the same calls (the stage
+// barriers are workgroup-wide). twd[e] = W_N^e.
+template <class T, int N, bool INV, bool SYNC_WAVE>
 __device__ __forceinline__ void fft_pencil(cx<T> (&v)[N / fft_threads(N)], cx<T>* lds, int t,
                                            const cx<T>* __restrict__ twd) {
-  FftStage<T, N, fft_threads(N), INV, 0>::run(v, lds, t, twd);
+  FftStage<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(v, lds, t, twd);
 }
 
 }  // namespace tw

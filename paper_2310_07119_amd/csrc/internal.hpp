@@ -98,7 +98,7 @@ hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, co
 
 // Supported transform lengths and the pencils a pass workgroup holds.
 bool pass_length_supported(int n);
-int pass_pencils_per_group(int n, bool fp32);
+int pass_pencils_per_group(int n, bool fp32, bool rows);
 bool step1d_length_supported(int n);
 
 }  // namespace tw

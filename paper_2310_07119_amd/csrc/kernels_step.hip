@@ -14,17 +14,34 @@
 #include "fft.hpp"
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace tw {
 
-template <class T, int N>
+// Pencils per workgroup. Row passes (stride 1): 4 wavefronts, every pencil
+// inside one wavefront, so the FFT exchanges are wavefront-local. Strided passes:
+// C adjacent pencils with lane = c + C t, so each global access instruction
+// covers C contiguous elements (>= 64 bytes); the exchanges are workgroup-wide.
+template <class T, int N, bool ROWS>
 __host__ __device__ constexpr int pencils_per_group() {
   constexpr int TPP = fft_threads(N);
-  int c = 256 / TPP;
-  const int coal = (sizeof(T) == 8) ? 8 : 16;  // >= 128 contiguous bytes on strided axes
-  if (c < coal) c = coal;
-  while (c > 1 && c * TPP > 1024) c /= 2;
-  while (c > 1 && (long)c * N * 2 * (long)sizeof(T) > 65536) c /= 2;
-  return c;
+  if constexpr (ROWS) {
+    return 4 * (64 / TPP);
+  } else {
+    int c = 256 / TPP;
+    if (c < 8) c = 8;
+    while (c > 1 && c * TPP > 512) c /= 2;
+    while (c > 1 && (long)c * fft_lds_stride(N) * 2 * (long)sizeof(T) > 96 * 1024) c /= 2;
+    return c;
+  }
+}
+template <class T, int N, bool ROWS>
+__host__ __device__ constexpr int pass_threads() {
+  return pencils_per_group<T, N, ROWS>() * fft_threads(N);
+}
+template <class T, int N, bool ROWS>
+__host__ __device__ constexpr size_t pass_lds_bytes() {
+  return (size_t)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 2 * sizeof(T) + 16 * sizeof(double);
 }
 
 template <class T>
@@ -48,19 +65,20 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-template <class T, int N, int MODE>
-__global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) pass_kernel(PassArgs a) {
+template <class T, int N, int MODE, bool ROWS>
+__global__ void __launch_bounds__((pass_threads<T, N, ROWS>())) pass_kernel(PassArgs a) {
   constexpr int TPP = fft_threads(N);
   constexpr int R = N / TPP;
-  constexpr int C = pencils_per_group<T, N>();
-  __shared__ cx<T> lds_all[C * N];
-  __shared__ double red[16];
+  constexpr int C = pencils_per_group<T, N, ROWS>();
+  constexpr bool SW = ROWS;  // wavefront-local exchanges
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * fft_lds_stride(N) * sizeof(cx<T>));
 
   const int tid = threadIdx.x;
-  const bool rows = (a.stride == 1);
-  const int c = rows ? tid / TPP : tid % C;
-  const int t = rows ? tid % TPP : tid / C;
-  cx<T>* lds = lds_all + c * N;
+  const int c = ROWS ? tid / TPP : tid % C;
+  const int t = ROWS ? tid % TPP : tid / C;
+  cx<T>* lds = lds_all + c * fft_lds_stride(N);
   const int64_t npencils = a.ncell / N;
   const int64_t p = (int64_t)blockIdx.x * C + c;
   const bool active = p < npencils;
@@ -81,11 +99,11 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
     }
   };
   auto drift = [&](cx<T> (&v)[R]) {
-    fft_pencil<T, N, false>(v, lds, t, twd);
+    fft_pencil<T, N, false, SW>(v, lds, t, twd);
     const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
-    fft_pencil<T, N, true>(v, lds, t, twd);
+    fft_pencil<T, N, true, SW>(v, lds, t, twd);
   };
 
   if constexpr (MODE == PASS_DRIFT) {
@@ -121,16 +139,16 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
     cx<T> zv[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) zv[m] = {(T)rho[0][m], (T)rho[1][m]};
-    fft_pencil<T, N, false>(zv, lds, t, twd);
+    fft_pencil<T, N, false, SW>(zv, lds, t, twd);
     store(reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell, zv);
   } else if constexpr (MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON) {
     cx<T>* zp = reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell;
     cx<T> zv[R];
     load(zp, zv);
     if constexpr (MODE == PASS_ZINV) {
-      fft_pencil<T, N, true>(zv, lds, t, twd);
+      fft_pencil<T, N, true, SW>(zv, lds, t, twd);
     } else {
-      fft_pencil<T, N, false>(zv, lds, t, twd);
+      fft_pencil<T, N, false, SW>(zv, lds, t, twd);
     }
     if constexpr (MODE == PASS_ZPOISSON) {
       const int64_t x0 = base % a.n[0];
@@ -148,13 +166,13 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
         const double g = (k2 == 0.0) ? 0.0 : a.green / k2;
         zv[m] = mul_d(zv[m], g);
       }
-      fft_pencil<T, N, true>(zv, lds, t, twd);
+      fft_pencil<T, N, true, SW>(zv, lds, t, twd);
     }
     store(zp, zv);
   } else if constexpr (MODE == PASS_KICK_DRIFT) {
     cx<T> zv[R];
     load(reinterpret_cast<const cx<T>*>(a.z) + pair * a.ncell, zv);
-    fft_pencil<T, N, true>(zv, lds, t, twd);
+    fft_pencil<T, N, true, SW>(zv, lds, t, twd);
     for (int k = 0; k < 2; ++k) {
       const int64_t f = 2 * pair + k;
       if (f >= a.nfield) break;
@@ -176,7 +194,7 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
       if (f >= a.nfield) break;
       cx<T> v[R];
       load(field_ptr<T>(a, f), v);
-      fft_pencil<T, N, false>(v, lds, t, twd);
+      fft_pencil<T, N, false, SW>(v, lds, t, twd);
       double s = 0.0;
 #pragma unroll
       for (int m = 0; m < R; ++m) s += k2a[t + TPP * m] * (double)abs2(v[m]);
@@ -194,7 +212,7 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
         zv[m] = mul_d(zv[m], (k2 == 0.0) ? 0.0 : a.green / k2);
       }
     }
-    fft_pencil<T, N, true>(zv, lds, t, twd);
+    fft_pencil<T, N, true, SW>(zv, lds, t, twd);
     for (int k = 0; k < 2; ++k) {
       const int64_t f = 2 * pair + k;
       if (f >= a.nfield) break;
@@ -209,26 +227,43 @@ __global__ void __launch_bounds__((pencils_per_group<T, N>() * fft_threads(N))) 
   }
 }
 
-template <class T, int N>
-static hipError_t launch_pass_tn(int mode, const PassArgs& a, hipStream_t s, int ny) {
-  constexpr int TPP = fft_threads(N);
-  constexpr int C = pencils_per_group<T, N>();
+template <class T, int N, bool ROWS>
+static hipError_t launch_pass_tnr(int mode, const PassArgs& a, hipStream_t s, int ny) {
+  constexpr int C = pencils_per_group<T, N, ROWS>();
+  constexpr size_t LDS = pass_lds_bytes<T, N, ROWS>();
   const int64_t npencils = a.ncell / N;
   dim3 grid((unsigned)((npencils + C - 1) / C), (unsigned)ny);
-  dim3 block(C * TPP);
+  dim3 block(pass_threads<T, N, ROWS>());
+  auto go = [&](auto kern) -> hipError_t {
+    if constexpr (LDS > 64 * 1024) {
+      static bool attr_set = false;  // per instantiation, once per process
+      if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+      }
+    }
+    hipLaunchKernelGGL(kern, grid, block, LDS, s, a);
+    return hipGetLastError();
+  };
   switch (mode) {
-    case PASS_DRIFT: hipLaunchKernelGGL((pass_kernel<T, N, PASS_DRIFT>), grid, block, 0, s, a); break;
-    case PASS_DRIFT_RHO: hipLaunchKernelGGL((pass_kernel<T, N, PASS_DRIFT_RHO>), grid, block, 0, s, a); break;
-    case PASS_ZFWD: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZFWD>), grid, block, 0, s, a); break;
-    case PASS_ZPOISSON: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZPOISSON>), grid, block, 0, s, a); break;
-    case PASS_ZINV: hipLaunchKernelGGL((pass_kernel<T, N, PASS_ZINV>), grid, block, 0, s, a); break;
-    case PASS_KICK_DRIFT: hipLaunchKernelGGL((pass_kernel<T, N, PASS_KICK_DRIFT>), grid, block, 0, s, a); break;
-    case PASS_RHO: hipLaunchKernelGGL((pass_kernel<T, N, PASS_RHO>), grid, block, 0, s, a); break;
-    case PASS_KIN_SUM: hipLaunchKernelGGL((pass_kernel<T, N, PASS_KIN_SUM>), grid, block, 0, s, a); break;
-    case PASS_POT_SUM: hipLaunchKernelGGL((pass_kernel<T, N, PASS_POT_SUM>), grid, block, 0, s, a); break;
+    case PASS_DRIFT: return go(pass_kernel<T, N, PASS_DRIFT, ROWS>);
+    case PASS_DRIFT_RHO: return go(pass_kernel<T, N, PASS_DRIFT_RHO, ROWS>);
+    case PASS_ZFWD: return go(pass_kernel<T, N, PASS_ZFWD, ROWS>);
+    case PASS_ZPOISSON: return go(pass_kernel<T, N, PASS_ZPOISSON, ROWS>);
+    case PASS_ZINV: return go(pass_kernel<T, N, PASS_ZINV, ROWS>);
+    case PASS_KICK_DRIFT: return go(pass_kernel<T, N, PASS_KICK_DRIFT, ROWS>);
+    case PASS_RHO: return go(pass_kernel<T, N, PASS_RHO, ROWS>);
+    case PASS_KIN_SUM: return go(pass_kernel<T, N, PASS_KIN_SUM, ROWS>);
+    case PASS_POT_SUM: return go(pass_kernel<T, N, PASS_POT_SUM, ROWS>);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+template <class T, int N>
+static hipError_t launch_pass_tn(int mode, const PassArgs& a, hipStream_t s, int ny) {
+  return a.stride == 1 ? launch_pass_tnr<T, N, true>(mode, a, s, ny) : launch_pass_tnr<T, N, false>(mode, a, s, ny);
 }
 
 template <class T>
@@ -249,21 +284,23 @@ bool pass_length_supported(int n) {
   return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
 }
 
-int pass_pencils_per_group(int n, bool fp32) {
-  auto pick = [&](auto tag) -> int {
+int pass_pencils_per_group(int n, bool fp32, bool rows) {
+  auto pick = [&](auto tag, auto r) -> int {
     using T = decltype(tag);
+    constexpr bool RW = decltype(r)::value;
     switch (n) {
-      case 16: return pencils_per_group<T, 16>();
-      case 32: return pencils_per_group<T, 32>();
-      case 64: return pencils_per_group<T, 64>();
-      case 128: return pencils_per_group<T, 128>();
-      case 256: return pencils_per_group<T, 256>();
-      case 512: return pencils_per_group<T, 512>();
-      case 1024: return pencils_per_group<T, 1024>();
+      case 16: return pencils_per_group<T, 16, RW>();
+      case 32: return pencils_per_group<T, 32, RW>();
+      case 64: return pencils_per_group<T, 64, RW>();
+      case 128: return pencils_per_group<T, 128, RW>();
+      case 256: return pencils_per_group<T, 256, RW>();
+      case 512: return pencils_per_group<T, 512, RW>();
+      case 1024: return pencils_per_group<T, 1024, RW>();
       default: return 0;
     }
   };
-  return fp32 ? pick(float{}) : pick(double{});
+  if (fp32) return rows ? pick(float{}, std::true_type{}) : pick(float{}, std::false_type{});
+  return rows ? pick(double{}, std::true_type{}) : pick(double{}, std::false_type{});
 }
 
 hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int ny) {
@@ -292,10 +329,10 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
   constexpr int TPP = fft_threads(N);
   constexpr int R = N / TPP;
   constexpr int C = fields_per_group_1d<T, N>();
-  __shared__ cx<T> lds_all[C * N];
+  __shared__ cx<T> lds_all[C * fft_lds_stride(N)];
   const int c = threadIdx.x / TPP;
   const int t = threadIdx.x % TPP;
-  cx<T>* lds = lds_all + c * N;
+  cx<T>* lds = lds_all + c * fft_lds_stride(N);
   const int64_t f = (int64_t)blockIdx.x * C + c;
   const bool active = f < nfield;
   cx<T>* fp = !active ? nullptr
@@ -312,10 +349,10 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
     g[m] = (kk == 0.0) ? 0.0 : green / kk;
   }
   auto drift = [&](const cx<double>* ph) {
-    fft_pencil<T, N, false>(v, lds, t, twd);
+    fft_pencil<T, N, false, true>(v, lds, t, twd);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
-    fft_pencil<T, N, true>(v, lds, t, twd);
+    fft_pencil<T, N, true, true>(v, lds, t, twd);
   };
 
   drift(ph_half);
@@ -323,10 +360,10 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
     cx<T> zv[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) zv[m] = {(T)(m_tot * (double)abs2(v[m]) - mean), (T)0};
-    fft_pencil<T, N, false>(zv, lds, t, twd);
+    fft_pencil<T, N, false, true>(zv, lds, t, twd);
 #pragma unroll
     for (int m = 0; m < R; ++m) zv[m] = mul_d(zv[m], g[m]);
-    fft_pencil<T, N, true>(zv, lds, t, twd);
+    fft_pencil<T, N, true, true>(zv, lds, t, twd);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], expmi<T>(kick * (double)zv[m].re));
     drift(s + 1 < nsteps ? ph_full : ph_half);
