@@ -60,6 +60,7 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
                 n_tot=wl["n_tot"], n_real=wl["n_real"], precision=precision)
     dev = torch.device("cuda:0")
     plan = Plan(p)
+    variant = plan.autotune()
     cl64 = torch.from_numpy(inputs.initial_field(wl["name"])).to(dev)
     psi = plan.empty_ensemble(dev)
     clt = torch.empty(p.shape, dtype=p.cdtype, device=dev)
@@ -99,6 +100,7 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
                        "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
                        "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches}
     res["kernel_ms"] = {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    res["strided_variant"] = variant
     plan.close()
     del psi, clt
     torch.cuda.empty_cache()
@@ -170,6 +172,7 @@ def main():
                    "classical_field": "evolved alongside, not counted in the work"},
         "roofline": main_run["roofline"],
         "kernel_ms": main_run["kernel_ms"],
+        "strided_pass_variant": main_run["strided_variant"],
     }
     if not args.no_fp32 and args.precision == "fp64":
         r32 = run_gpu(wl, "fp32", args.steps, args.warmup)

@@ -55,7 +55,8 @@ typedef enum { TW_FP64 = 0, TW_FP32_SPLIT = 1 } tw_precision;
 typedef struct {
   int32_t dim;        /* D in {1,2,3} */
   int32_t n[3];       /* points per axis, x first; unused axes must be 1.
-                         Supported: powers of two, 16..1024 (D=1: 8..1024) */
+                         Supported: 16, 24, 32, 48, 64, 96, 128, 192, 256,
+                         384, 512, 1024 (D=1 also 8) */
   double box[3];      /* box length per axis, > 0 (unused axes ignored) */
   double hbar_m;      /* hbar/m > 0 */
   double G;           /* Newton constant >= 0 (0 = free Schrodinger equation) */
@@ -126,6 +127,20 @@ typedef struct {
  *   psi_classical : device, [N] in the plan's precision, or NULL. */
 int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
                const tw_moments_out* out, void* stream);
+
+/* Autotune the kernel organisation of the passes along strided axes (y, z).
+ * Returns at once if the plan's choice is already settled (tuning cache entry,
+ * TW_COLS_VARIANT override, or an earlier call). Otherwise it times both
+ * available organisations on scratch buffers of this plan's shape
+ * (up to 32 pairs of realizations; allocates and frees them), keeps the faster
+ * for this plan and records it in the tuning cache ($TW_TUNE_CACHE, else
+ * $XDG_CACHE_HOME or $HOME/.cache, file twa_mi355x_tune.json), which later
+ * tw_plan_create calls with the same device, grid, precision and ensemble
+ * size read. Synchronous. *variant_out (may be NULL) receives the choice
+ * (0 = pencils interleaved across wavefronts, 1 = LDS tiles). Results do not
+ * depend on the choice beyond rounding. The environment variable
+ * TW_COLS_VARIANT=0|1, read by tw_plan_create, forces a choice instead. */
+int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream);
 
 /* Kernel timing for measurement tools (not needed for the method itself).
  * When enabled, every kernel launched by tw_sample / tw_step / tw_moments on

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -113,9 +114,22 @@ int check_ptr(const Plan& P, const void* p, const char* name, bool nullable) {
 
 // groups (workgroups along x) of a pass along `axis`
 int pass_groups(const Plan& P, int axis) {
-  const int c = pass_pencils_per_group(P.n[axis], P.fp32, axis == 0);
+  const int c = pass_pencils_per_group(P.n[axis], P.fp32, axis == 0, P.cols_variant);
   const int64_t np = P.ncell / P.n[axis];
   return (int)((np + c - 1) / c);
+}
+
+// Largest number of pass workgroups along any axis over both strided-pass
+// organisations: the per-group energy partials are laid out with this stride.
+int64_t partial_gmax(const Plan& P) {
+  int64_t gmax = 1;
+  if (!P.z) return gmax;
+  for (int v = 0; v < 2; ++v) {
+    Plan Q = P;
+    Q.cols_variant = v;
+    for (int d = 0; d < P.dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(Q, d));
+  }
+  return gmax;
 }
 
 PassArgs base_args(const Plan& P, void* psi, void* psi_cl, int64_t nfield) {
@@ -133,17 +147,27 @@ PassArgs base_args(const Plan& P, void* psi, void* psi_cl, int64_t nfield) {
   }
   a.green = -4.0 * M_PI * P.p.G / (double)P.ncell;
   a.m_tot = P.p.m_tot;
+  a.variant = P.cols_variant;
   return a;
 }
 
-hipError_t pass(Plan& P, PassArgs a, int mode, int axis, const void* phase, hipStream_t s) {
+// One pass over pairs [pair0, pair0 + npairs) (npairs < 0: every pair).
+hipError_t pass(Plan& P, PassArgs a, int mode, int axis, const void* phase, hipStream_t s, int64_t pair0 = 0,
+                int64_t npairs = -1) {
   a.axis = axis;
   a.stride = axis_stride(P, axis);
   a.twd = P.twd[axis];
   a.phase = phase;
-  const int64_t npairs = (a.nfield + 1) / 2;
+  a.pair0 = pair0;
+  if (npairs < 0) npairs = (a.nfield + 1) / 2 - pair0;
   return timed(P, mode, s, [&] { return launch_pass(P, mode, a, s, (int)npairs); });
 }
+
+// Pairs advanced together through all steps. Chunks small enough to stay in
+// the 256 MB Infinity Cache were measured slower on MI355X (the passes are
+// latency-bound and lose more to smaller grids than they gain from the cache),
+// so by default the whole ensemble is one chunk.
+int64_t default_chunk_pairs(const Plan& P) { return P.npairs; }
 
 }  // namespace
 }  // namespace tw
@@ -165,7 +189,6 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
     if (d < pr->dim) {
       if (pr->n[d] < 1) return fail(TW_EINVAL, "n[%d] must be positive", d);
       if (!(pr->box[d] > 0.0) || !std::isfinite(pr->box[d])) return fail(TW_EINVAL, "box[%d] must be > 0", d);
-      if (!is_pow2(pr->n[d])) return fail(TW_EUNSUPPORTED, "n[%d]=%d is not a power of two", d, pr->n[d]);
       const bool ok = pr->dim == 1 ? step1d_length_supported(pr->n[d]) : pass_length_supported(pr->n[d]);
       if (!ok) return fail(TW_EUNSUPPORTED, "n[%d]=%d outside the supported lengths", d, pr->n[d]);
     } else if (pr->n[d] != 1) {
@@ -201,6 +224,11 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   P->elem = P->fp32 ? 8 : 16;
   P->nfield = pr->n_real + 1;
   P->npairs = (P->nfield + 1) / 2;
+  P->chunk_pairs = 0;  // 0: default_chunk_pairs
+  if (const char* env = getenv("TW_CHUNK_PAIRS")) P->chunk_pairs = atoll(env);
+  // strided-pass organisation: tuning cache if it has this shape, else the
+  // usual winner (LDS tiles for FP32, interleaved pencils for FP64)
+  P->cols_variant = P->fp32 ? 1 : 0;
   if (hipGetDevice(&P->device) != hipSuccess) {
     free_plan(P);
     return fail(TW_EHIP, "no HIP device");
@@ -257,9 +285,28 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   const bool need_z = pr->dim >= 2 || pass_length_supported(P->n[0]);
   if (need_z) ALLOC(P->z, P->elem * (size_t)P->npairs * (size_t)P->ncell);
   ALLOC(P->rho_mean, sizeof(double) * P->nfield);
+  if (pr->dim >= 2) {
+    const int v = tune_cache_lookup(tune_key(*P));
+    if (v >= 0) {
+      P->cols_variant = v;
+      P->tuned = 1;
+    }
+  }
+  if (const char* env = getenv("TW_COLS_VARIANT")) {  // explicit override (tests, experiments)
+    const int v = atoi(env);
+    if (v == 0 || v == 1) {
+      P->cols_variant = v;
+      P->tuned = 1;
+    }
+  }
   int64_t gmax = 1;
   if (need_z)
-    for (int d = 0; d < pr->dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(*P, d));
+    for (int v = 0; v < 2; ++v) {  // partial sums sized for either organisation
+      const int keep = P->cols_variant;
+      P->cols_variant = v;
+      for (int d = 0; d < pr->dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(*P, d));
+      P->cols_variant = keep;
+    }
   const int64_t nwaves = (P->ncell + 63) / 64;
   const int64_t energy_part = 4 * P->nfield * gmax + P->nfield;
   const int64_t mom_part = pr->n_real * nwaves + 3 * nwaves + pr->n_real + 8;
@@ -326,28 +373,36 @@ int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, vo
   a.kick = kick;
   a.rho_mean = P.fp32 ? P.rho_mean : nullptr;
   const int D = P.dim;
-  int o[3] = {0, 1, 2};
-  // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
-  for (int i = D - 1; i >= 1; --i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 0), s));
-  TW_HIP(pass(P, a, PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0), s));
-  for (int64_t st = 0; st < nsteps; ++st) {
-    const bool last = (st + 1 == nsteps);
-    const int full = last ? 0 : 1;
-    // rest of the forward transform of rho, Green's function, inverse (all but o[0])
-    for (int i = 1; i < D - 1; ++i) TW_HIP(pass(P, a, PASS_ZFWD, o[i], nullptr, s));
-    TW_HIP(pass(P, a, PASS_ZPOISSON, o[D - 1], nullptr, s));
-    for (int i = D - 2; i >= 1; --i) TW_HIP(pass(P, a, PASS_ZINV, o[i], nullptr, s));
-    // last inverse along o[0] -> V, kick, drift along o[0]
-    TW_HIP(pass(P, a, PASS_KICK_DRIFT, o[0], phase_slot(o[0], full), s));
-    if (!last) {
-      for (int i = 1; i < D - 1; ++i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 1), s));
-      TW_HIP(pass(P, a, PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1), s));
-      // reverse the axis order so the density transform just made is the first one
-      int r[3] = {0, 0, 0};
-      for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
-      for (int i = 0; i < D; ++i) o[i] = r[i];
-    } else {
-      for (int i = 1; i < D; ++i) TW_HIP(pass(P, a, PASS_DRIFT, o[i], phase_slot(o[i], 0), s));
+  const int64_t npairs = (nfield + 1) / 2;
+  const int64_t chunk = P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P);
+  // Realizations are independent: each chunk of pairs runs every step before
+  // the next chunk starts.
+  for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
+    const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
+    auto run = [&](int mode, int axis, const void* phase) { return pass(P, a, mode, axis, phase, s, c0, nc); };
+    int o[3] = {0, 1, 2};
+    // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
+    for (int i = D - 1; i >= 1; --i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
+    TW_HIP(run(PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0)));
+    for (int64_t st = 0; st < nsteps; ++st) {
+      const bool last = (st + 1 == nsteps);
+      const int full = last ? 0 : 1;
+      // rest of the forward transform of rho, Green's function, inverse (all but o[0])
+      for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_ZFWD, o[i], nullptr));
+      TW_HIP(run(PASS_ZPOISSON, o[D - 1], nullptr));
+      for (int i = D - 2; i >= 1; --i) TW_HIP(run(PASS_ZINV, o[i], nullptr));
+      // last inverse along o[0] -> V, kick, drift along o[0]
+      TW_HIP(run(PASS_KICK_DRIFT, o[0], phase_slot(o[0], full)));
+      if (!last) {
+        for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 1)));
+        TW_HIP(run(PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1)));
+        // reverse the axis order so the density transform just made is the first one
+        int r[3] = {0, 0, 0};
+        for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
+        for (int i = 0; i < D; ++i) o[i] = r[i];
+      } else {
+        for (int i = 1; i < D; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
+      }
     }
   }
   return TW_OK;
@@ -368,11 +423,8 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_momen
     void* cl_m = const_cast<void*>(psi_cl);
     PassArgs a = base_args(P, psi_m, cl_m, nfield);
     int ng[4] = {1, 1, 1, 1};
-    int64_t gmax = 1;
-    for (int d = 0; d < P.dim; ++d) {
-      ng[d] = pass_groups(P, d);
-      gmax = std::max<int64_t>(gmax, ng[d]);
-    }
+    for (int d = 0; d < P.dim; ++d) ng[d] = pass_groups(P, d);
+    const int64_t gmax = partial_gmax(P);
     ng[3] = ng[0];
     const int64_t gstride = P.nfield * gmax;
     energy_dev = P.partial + 4 * gstride;
@@ -401,13 +453,76 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_momen
   }
   Plan Q = P;
   // the moment reductions use the region after the energy partials
-  {
-    int64_t gmax = 1;
-    if (P.z)
-      for (int d = 0; d < P.dim; ++d) gmax = std::max<int64_t>(gmax, pass_groups(P, d));
-    Q.partial = P.partial + 4 * P.nfield * gmax + P.nfield;
-  }
+  Q.partial = P.partial + 4 * P.nfield * partial_gmax(P) + P.nfield;
   TW_HIP(timed(P, KIND_MOMENTS, s, [&] { return launch_moments(Q, psi, psi_cl, out, energy_dev, s); }));
+  return TW_OK;
+}
+
+int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (P.dim == 1 || P.tuned) {  // no strided passes, or already chosen (cache / override / earlier call)
+    P.tuned = 1;
+    if (variant_out) *variant_out = P.cols_variant;
+    return TW_OK;
+  }
+  // scratch ensemble of up to 32 pairs (enough workgroups to fill the device)
+  const int64_t npt = std::min<int64_t>(P.npairs, 32);
+  const int64_t nf = 2 * npt;
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, (size_t)nf * P.ncell * P.elem) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TW_ENOMEM, "autotune scratch allocation failed");
+  }
+  struct Free {
+    void* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{tmp};
+  TW_HIP(hipMemsetAsync(tmp, 0, (size_t)nf * P.ncell * P.elem, s));
+  TW_HIP(hipMemsetAsync(P.z, 0, (size_t)npt * P.ncell * P.elem, s));
+  auto phase_slot = [&](int axis, int full) -> void* {
+    return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
+  };
+  for (int d = 0; d < P.dim; ++d) {
+    TW_HIP(launch_phase_table(P, d, 5e-5, phase_slot(d, 0), s));
+    TW_HIP(launch_phase_table(P, d, 1e-4, phase_slot(d, 1), s));
+  }
+  Plan Q = P;
+  Q.p.n_real = nf;
+  Q.profiling = false;
+  PassArgs a = base_args(Q, tmp, nullptr, nf);
+  a.kick = 1e-4;
+  hipEvent_t e0, e1;
+  TW_HIP(hipEventCreate(&e0));
+  TW_HIP(hipEventCreate(&e1));
+  double us[2] = {0.0, 0.0};
+  const int modes[5] = {PASS_DRIFT_RHO, PASS_ZPOISSON, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
+  int rc = TW_OK;
+  for (int v = 0; v < 2 && rc == TW_OK; ++v) {
+    Q.cols_variant = v;
+    a.variant = v;
+    for (int rep = 0; rep < 4 && rc == TW_OK; ++rep) {  // rep 0 warms up
+      if (hipEventRecord(e0, s) != hipSuccess) rc = fail(TW_EHIP, "event record failed");
+      for (int d = 1; d < P.dim && rc == TW_OK; ++d)
+        for (int m = 0; m < 5 && rc == TW_OK; ++m) {
+          hipError_t e = pass(Q, a, modes[m], d, phase_slot(d, 1), s, 0, npt);
+          if (e != hipSuccess) rc = fail(TW_EHIP, "autotune pass: %s", hipGetErrorString(e));
+        }
+      float ms = 0.f;
+      if (rc == TW_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(TW_EHIP, "event timing failed");
+      if (rep > 0) us[v] += 1e3 * ms / 3.0;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != TW_OK) return rc;
+  P.cols_variant = us[1] < us[0] ? 1 : 0;
+  P.tuned = 1;
+  tune_cache_store(tune_key(P), P.cols_variant, us);
+  if (variant_out) *variant_out = P.cols_variant;
   return TW_OK;
 }
 

@@ -29,28 +29,45 @@
 namespace tw {
 
 // ---------------------------------------------------------------- plans
-// Power-of-two lengths: 8 points per thread (N <= 512, at most 64 threads per
-// pencil), 16 for N = 1024 (so a pencil never spans two wavefronts); radix-8
-// stages and one smaller last stage.
-__host__ __device__ constexpr int fft_points_per_thread(int N) { return N > 512 ? 16 : (N >= 8 ? 8 : N); }
+// Lengths with compiled pass kernels (X-macro); 1D resident kernels also take 8.
+#define TW_PASS_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+#define TW_STEP1D_LENGTHS(X) X(8) TW_PASS_LENGTHS(X)
+// Supported lengths: powers of two 8..1024 and 3*2^k (24, 48, 96, 192, 384).
+// Powers of two: 8 points per thread (N <= 512, at most 64 threads per pencil),
+// 16 for N = 1024 (so a pencil never spans two wavefronts); radix-8 stages and
+// one smaller last stage. 3*2^k: 12 points per thread, radix-4 stages, then
+// radix 2 if needed, then one radix-6 stage (e.g. 96 = 4*4*6, 48 = 4*2*6).
+__host__ __device__ constexpr bool fft_is_pow2(int N) { return N > 0 && (N & (N - 1)) == 0; }
+__host__ __device__ constexpr bool fft_length_ok(int N) {
+  return (fft_is_pow2(N) && N >= 8 && N <= 1024) || N == 24 || N == 48 || N == 96 || N == 192 || N == 384;
+}
+__host__ __device__ constexpr int fft_points_per_thread(int N) {
+  return fft_is_pow2(N) ? (N > 512 ? 16 : (N >= 8 ? 8 : N)) : 12;
+}
 __host__ __device__ constexpr int fft_threads(int N) { return N / fft_points_per_thread(N); }
 __host__ __device__ constexpr int fft_lds_stride(int N) { return N + N / 8 + 1; }
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 3); }
 
-__host__ __device__ constexpr int fft_next_radix(int rem) { return (rem % 8 == 0) ? 8 : rem; }
+// radix of the next stage when `rem` points of the transform are left
+__host__ __device__ constexpr int fft_next_radix(int N, int rem) {
+  if (fft_is_pow2(N)) return (rem % 8 == 0) ? 8 : rem;
+  if (rem == 6) return 6;
+  if (rem == 12) return 2;
+  return 4;
+}
 __host__ __device__ constexpr int fft_num_stages(int N, int R) {
   int s = 0;
   int rem = N;
   while (rem > 1) {
-    rem /= fft_next_radix(rem);
+    rem /= fft_next_radix(N, rem);
     ++s;
   }
   return s;
 }
 __host__ __device__ constexpr int fft_stage_radix(int N, int R, int stage) {
   int rem = N;
-  for (int s = 0; s < stage; ++s) rem /= fft_next_radix(rem);
-  return fft_next_radix(rem);
+  for (int s = 0; s < stage; ++s) rem /= fft_next_radix(N, rem);
+  return fft_next_radix(N, rem);
 }
 __host__ __device__ constexpr int fft_stage_ns(int N, int R, int stage) {
   int ns = 1;
@@ -95,6 +112,48 @@ struct Butterfly<T, 4, INV> {
 };
 
 template <class T, bool INV>
+struct Butterfly<T, 3, INV> {
+  // X0 = a+b+c; X1,2 = a - (b+c)/2 -+ i (sqrt3/2)(b-c) for the forward sign
+  static __device__ __forceinline__ void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
+    const T h = (T)0.86602540378443864676372317075294;
+    const cx<T> t = b + c;
+    const cx<T> m = {a.re - (T)0.5 * t.re, a.im - (T)0.5 * t.im};
+    const cx<T> d = b - c;
+    const cx<T> q = INV ? cx<T>{-h * d.im, h * d.re} : cx<T>{h * d.im, -h * d.re};
+    a = a + t;
+    b = m + q;
+    c = m - q;
+  }
+  template <int RR>
+  static __device__ __forceinline__ void run(cx<T> (&v)[RR], int i0, int step) {
+    dft3(v[i0], v[i0 + step], v[i0 + 2 * step]);
+  }
+};
+
+template <class T, bool INV>
+struct Butterfly<T, 6, INV> {
+  // even/odd split: X_k = E_k + W6^k O_k, X_{k+3} = E_k - W6^k O_k (k = 0, 1, 2)
+  template <int RR>
+  static __device__ __forceinline__ void run(cx<T> (&v)[RR], int i0, int step) {
+    cx<T> e0 = v[i0], e1 = v[i0 + 2 * step], e2 = v[i0 + 4 * step];
+    cx<T> o0 = v[i0 + step], o1 = v[i0 + 3 * step], o2 = v[i0 + 5 * step];
+    Butterfly<T, 3, INV>::dft3(e0, e1, e2);
+    Butterfly<T, 3, INV>::dft3(o0, o1, o2);
+    const T h = (T)0.86602540378443864676372317075294;
+    // W6 = 1/2 -+ i sqrt3/2, W6^2 = -1/2 -+ i sqrt3/2 (forward sign first)
+    const cx<T> w1 = INV ? cx<T>{(T)0.5, h} : cx<T>{(T)0.5, -h};
+    const cx<T> w2 = INV ? cx<T>{(T)-0.5, h} : cx<T>{(T)-0.5, -h};
+    const cx<T> p1 = cmul(o1, w1), p2 = cmul(o2, w2);
+    v[i0] = e0 + o0;
+    v[i0 + 3 * step] = e0 - o0;
+    v[i0 + step] = e1 + p1;
+    v[i0 + 4 * step] = e1 - p1;
+    v[i0 + 2 * step] = e2 + p2;
+    v[i0 + 5 * step] = e2 - p2;
+  }
+};
+
+template <class T, bool INV>
 struct Butterfly<T, 8, INV> {
   template <int RR>
   static __device__ __forceinline__ void run(cx<T> (&v)[RR], int i0, int step) {
@@ -125,6 +184,68 @@ struct Butterfly<T, 8, INV> {
   }
 };
 
+// --------------------------------------------------------- twiddle cache
+// Per-thread twiddles of every stage, loaded once from the table into
+// registers (a thread's butterfly indices are the same for every pencil it
+// transforms). Stage s, butterfly i, input r >= 1 uses W_N^(r (j mod Ns) N/(Ns Rs)).
+// With CACHED = false only the table pointer is kept and each stage reads its
+// twiddles when it runs (fewer registers, more memory latency per stage).
+template <class T, int N, bool CACHED_ = true>
+struct TwiddleCache {
+  static constexpr bool CACHED = CACHED_;
+  static constexpr int TPP = fft_threads(N);
+  static constexpr int R = N / TPP;
+  static constexpr int NS = fft_num_stages(N, R);
+  static constexpr int stage_count(int s) {
+    return fft_stage_ns(N, R, s) > 1 ? (R / fft_stage_radix(N, R, s)) * (fft_stage_radix(N, R, s) - 1) : 0;
+  }
+  static constexpr int stage_offset(int s) {
+    int o = 0;
+    for (int q = 0; q < s; ++q) o += stage_count(q);
+    return o;
+  }
+  static constexpr int COUNT = stage_offset(NS);
+  static constexpr int SIZE = (CACHED && COUNT > 0) ? COUNT : 1;
+  cx<T> w[SIZE];
+  const cx<T>* table;
+  int t_;
+
+  __device__ __forceinline__ void load(const cx<T>* __restrict__ twd, int t) {
+    table = twd;
+    t_ = t;
+    if constexpr (CACHED) load_stage<0>(twd, t);
+  }
+  // twiddle for stage S, butterfly i, input r
+  template <int S>
+  __device__ __forceinline__ cx<T> get(int i, int r) const {
+    if constexpr (CACHED) {
+      return w[stage_offset(S) + i * (fft_stage_radix(N, R, S) - 1) + (r - 1)];
+    } else {
+      constexpr int RS = fft_stage_radix(N, R, S);
+      constexpr int NSB = fft_stage_ns(N, R, S);
+      const int jm = (t_ + TPP * i) % NSB;
+      return table[r * jm * (N / (NSB * RS))];
+    }
+  }
+  template <int S>
+  __device__ __forceinline__ void load_stage(const cx<T>* __restrict__ twd, int t) {
+    if constexpr (S < NS) {
+      constexpr int RS = fft_stage_radix(N, R, S);
+      constexpr int NSB = fft_stage_ns(N, R, S);
+      constexpr int NB = R / RS;
+      if constexpr (NSB > 1) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int jm = (t + TPP * i) % NSB;
+#pragma unroll
+          for (int r = 1; r < RS; ++r) w[stage_offset(S) + i * (RS - 1) + (r - 1)] = twd[r * jm * (N / (NSB * RS))];
+        }
+      }
+      load_stage<S + 1>(twd, t);
+    }
+  }
+};
+
 // ---------------------------------------------------------------- stages
 template <bool SYNC_WAVE>
 __device__ __forceinline__ void fft_sync() {
@@ -146,7 +267,7 @@ struct FftStage {
   static constexpr int NB = R / RS;                   // butterflies per thread
   static_assert(R % RS == 0, "every stage radix must divide the points per thread");
 
-  static __device__ __forceinline__ void run(cx<T> (&v)[R], cx<T>* lds, int t, const cx<T>* __restrict__ twd) {
+  static __device__ __forceinline__ void run(cx<T> (&v)[R], cx<T>* lds, int t, const TwiddleCache<T, N>& tc) {
     if constexpr (S > 0) {
       fft_sync<SW>();  // previous stage's LDS writes are visible
 #pragma unroll
@@ -158,12 +279,10 @@ struct FftStage {
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int j = t + TPP * i;
       if constexpr (NSB > 1) {
-        const int jm = j % NSB;
 #pragma unroll
         for (int r = 1; r < RS; ++r) {
-          const cx<T> w = twd[r * jm * (N / (NSB * RS))];
+          const cx<T> w = tc.template get<S>(i, r);
           v[i + r * NB] = INV ? cmulc(v[i + r * NB], w) : cmul(v[i + r * NB], w);
         }
       }
@@ -178,7 +297,7 @@ struct FftStage {
 #pragma unroll
         for (int r = 0; r < RS; ++r) lds[lds_pad(base + r * NSB)] = v[i + r * NB];
       }
-      FftStage<T, N, TPP, INV, SW, S + 1>::run(v, lds, t, twd);
+      FftStage<T, N, TPP, INV, SW, S + 1>::run(v, lds, t, tc);
     }
   }
 };
@@ -186,11 +305,12 @@ struct FftStage {
 // Transform the pencil held in v (natural layout) in place. `lds` is this
 // pencil's private buffer of fft_lds_stride(N) elements. With SYNC_WAVE =
 // false every thread of the workgroup must make the same calls (the stage
-// barriers are workgroup-wide). twd[e] = W_N^e.
+// barriers are workgroup-wide). `tc` holds this thread's twiddles (loaded from
+// the table twd[e] = W_N^e by TwiddleCache::load).
 template <class T, int N, bool INV, bool SYNC_WAVE>
 __device__ __forceinline__ void fft_pencil(cx<T> (&v)[N / fft_threads(N)], cx<T>* lds, int t,
-                                           const cx<T>* __restrict__ twd) {
-  FftStage<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(v, lds, t, twd);
+                                           const TwiddleCache<T, N>& tc) {
+  FftStage<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(v, lds, t, tc);
 }
 
 }  // namespace tw

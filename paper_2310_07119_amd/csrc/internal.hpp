@@ -4,7 +4,7 @@
 #include <stdint.h>
 #include <string>
 
-#include "../../include/tw.h"
+#include "tw.h"
 
 namespace tw {
 
@@ -28,7 +28,8 @@ struct PassArgs {
   const double* rho_mean;  // [nfield] density mean subtracted before the transform, or nullptr
   double* partial;         // reduction output for diagnostic passes
   int32_t pot_green;       // PASS_POT_SUM: apply G(k) along the axis before the inverse (D = 1)
-  int32_t pad_;
+  int32_t variant;         // strided passes: 0 = pencil-interleaved, 1 = LDS tiles (see kernels_cols.hip)
+  int64_t pair0;           // first pair of this launch (blockIdx.y + pair0)
 };
 
 enum PassMode : int {
@@ -67,6 +68,9 @@ struct Plan {
   double* partial;       // reductions
   size_t partial_len;    // doubles
   double* scratch_small; // [64] misc device scalars
+  int64_t chunk_pairs;   // pairs advanced through all steps together (cache residency)
+  int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
+  int32_t tuned;         // cols_variant came from a measurement or the tuning cache
   // kernel timing (tw_plan_set_profiling)
   bool profiling;
   void* prof;            // opaque event record (api.hip)
@@ -84,6 +88,8 @@ enum KernelKind : int {
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs_or_fields);
+hipError_t launch_pass_cols(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs);
+int cols_pencils_per_group(int n, bool fp32);
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* phase_half, const void* phase_full, double kick, hipStream_t s);
 hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hipStream_t s);
@@ -96,9 +102,14 @@ hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t 
 hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
                           const double* energy_dev, hipStream_t s);
 
+// Autotuner cache (tune.hip).
+std::string tune_key(const Plan& P);
+int tune_cache_lookup(const std::string& key);
+void tune_cache_store(const std::string& key, int variant, const double us[2]);
+
 // Supported transform lengths and the pencils a pass workgroup holds.
 bool pass_length_supported(int n);
-int pass_pencils_per_group(int n, bool fp32, bool rows);
+int pass_pencils_per_group(int n, bool fp32, bool rows, int variant);
 bool step1d_length_supported(int n);
 
 }  // namespace tw

@@ -13,218 +13,16 @@
 #include "common.hpp"
 #include "fft.hpp"
 #include "internal.hpp"
+#include "pass_common.hpp"
+#include "pass_rows.hpp"
 
 #include <type_traits>
 
 namespace tw {
 
-// Pencils per workgroup. Row passes (stride 1): 4 wavefronts, every pencil
-// inside one wavefront, so the FFT exchanges are wavefront-local. Strided passes:
-// C adjacent pencils with lane = c + C t, so each global access instruction
-// covers C contiguous elements (>= 64 bytes); the exchanges are workgroup-wide.
-template <class T, int N, bool ROWS>
-__host__ __device__ constexpr int pencils_per_group() {
-  constexpr int TPP = fft_threads(N);
-  if constexpr (ROWS) {
-    return 4 * (64 / TPP);
-  } else {
-    int c = 256 / TPP;
-    if (c < 8) c = 8;
-    while (c > 1 && c * TPP > 512) c /= 2;
-    while (c > 1 && (long)c * fft_lds_stride(N) * 2 * (long)sizeof(T) > 96 * 1024) c /= 2;
-    return c;
-  }
-}
-template <class T, int N, bool ROWS>
-__host__ __device__ constexpr int pass_threads() {
-  return pencils_per_group<T, N, ROWS>() * fft_threads(N);
-}
-template <class T, int N, bool ROWS>
-__host__ __device__ constexpr size_t pass_lds_bytes() {
-  return (size_t)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 2 * sizeof(T) + 16 * sizeof(double);
-}
-
-template <class T>
-__device__ __forceinline__ cx<T>* field_ptr(const PassArgs& a, int64_t f) {
-  return f < a.n_real ? reinterpret_cast<cx<T>*>(a.psi) + f * a.ncell : reinterpret_cast<cx<T>*>(a.psi_cl);
-}
-
-// Sum of `x` over the workgroup; result valid in thread 0. `red` holds one
-// double per wave.
-__device__ __forceinline__ double block_sum(double x, double* red) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = x;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) s += red[w];
-  }
-  return s;
-}
-
 template <class T, int N, int MODE, bool ROWS>
 __global__ void __launch_bounds__((pass_threads<T, N, ROWS>())) pass_kernel(PassArgs a) {
-  constexpr int TPP = fft_threads(N);
-  constexpr int R = N / TPP;
-  constexpr int C = pencils_per_group<T, N, ROWS>();
-  constexpr bool SW = ROWS;  // wavefront-local exchanges
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
-  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * fft_lds_stride(N) * sizeof(cx<T>));
-
-  const int tid = threadIdx.x;
-  const int c = ROWS ? tid / TPP : tid % C;
-  const int t = ROWS ? tid % TPP : tid / C;
-  cx<T>* lds = lds_all + c * fft_lds_stride(N);
-  const int64_t npencils = a.ncell / N;
-  const int64_t p = (int64_t)blockIdx.x * C + c;
-  const bool active = p < npencils;
-  const int64_t pp = active ? p : 0;
-  const int64_t base = (pp % a.stride) + (pp / a.stride) * a.stride * N;
-  const int64_t stride = a.stride;
-  const int64_t pair = blockIdx.y;
-  const cx<T>* __restrict__ twd = reinterpret_cast<const cx<T>*>(a.twd);
-
-  auto load = [&](const cx<T>* f, cx<T> (&v)[R]) {
-#pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = active ? f[base + (int64_t)(t + TPP * m) * stride] : cx<T>{(T)0, (T)0};
-  };
-  auto store = [&](cx<T>* f, const cx<T> (&v)[R]) {
-    if (active) {
-#pragma unroll
-      for (int m = 0; m < R; ++m) f[base + (int64_t)(t + TPP * m) * stride] = v[m];
-    }
-  };
-  auto drift = [&](cx<T> (&v)[R]) {
-    fft_pencil<T, N, false, SW>(v, lds, t, twd);
-    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
-#pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
-    fft_pencil<T, N, true, SW>(v, lds, t, twd);
-  };
-
-  if constexpr (MODE == PASS_DRIFT) {
-    for (int k = 0; k < 2; ++k) {
-      const int64_t f = 2 * pair + k;
-      if (f >= a.nfield) break;
-      cx<T>* fp = field_ptr<T>(a, f);
-      cx<T> v[R];
-      load(fp, v);
-      drift(v);
-      store(fp, v);
-    }
-  } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
-    double rho[2][R];
-    for (int k = 0; k < 2; ++k) {
-      const int64_t f = 2 * pair + k;
-      if (f < a.nfield) {
-        cx<T>* fp = field_ptr<T>(a, f);
-        cx<T> v[R];
-        load(fp, v);
-        if constexpr (MODE == PASS_DRIFT_RHO) {
-          drift(v);
-          store(fp, v);
-        }
-        const double mean = a.rho_mean ? a.rho_mean[f] : 0.0;
-#pragma unroll
-        for (int m = 0; m < R; ++m) rho[k][m] = a.m_tot * (double)abs2(v[m]) - mean;
-      } else {
-#pragma unroll
-        for (int m = 0; m < R; ++m) rho[k][m] = 0.0;
-      }
-    }
-    cx<T> zv[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) zv[m] = {(T)rho[0][m], (T)rho[1][m]};
-    fft_pencil<T, N, false, SW>(zv, lds, t, twd);
-    store(reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell, zv);
-  } else if constexpr (MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON) {
-    cx<T>* zp = reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell;
-    cx<T> zv[R];
-    load(zp, zv);
-    if constexpr (MODE == PASS_ZINV) {
-      fft_pencil<T, N, true, SW>(zv, lds, t, twd);
-    } else {
-      fft_pencil<T, N, false, SW>(zv, lds, t, twd);
-    }
-    if constexpr (MODE == PASS_ZPOISSON) {
-      const int64_t x0 = base % a.n[0];
-      const int64_t y0 = (base / a.n[0]) % a.n[1];
-      const int64_t z0 = base / ((int64_t)a.n[0] * a.n[1]);
-      const int64_t co[3] = {x0, y0, z0};
-      double k2o = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (d != a.axis) k2o += a.k2[d][co[d]];
-      const double* __restrict__ k2a = a.k2[a.axis];
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const double k2 = k2o + k2a[t + TPP * m];
-        const double g = (k2 == 0.0) ? 0.0 : a.green / k2;
-        zv[m] = mul_d(zv[m], g);
-      }
-      fft_pencil<T, N, true, SW>(zv, lds, t, twd);
-    }
-    store(zp, zv);
-  } else if constexpr (MODE == PASS_KICK_DRIFT) {
-    cx<T> zv[R];
-    load(reinterpret_cast<const cx<T>*>(a.z) + pair * a.ncell, zv);
-    fft_pencil<T, N, true, SW>(zv, lds, t, twd);
-    for (int k = 0; k < 2; ++k) {
-      const int64_t f = 2 * pair + k;
-      if (f >= a.nfield) break;
-      cx<T>* fp = field_ptr<T>(a, f);
-      cx<T> v[R];
-      load(fp, v);
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const double V = (double)(k == 0 ? zv[m].re : zv[m].im);
-        v[m] = cmul(v[m], expmi<T>(a.kick * V));
-      }
-      drift(v);
-      store(fp, v);
-    }
-  } else if constexpr (MODE == PASS_KIN_SUM) {
-    const double* __restrict__ k2a = a.k2[a.axis];
-    for (int k = 0; k < 2; ++k) {
-      const int64_t f = 2 * pair + k;
-      if (f >= a.nfield) break;
-      cx<T> v[R];
-      load(field_ptr<T>(a, f), v);
-      fft_pencil<T, N, false, SW>(v, lds, t, twd);
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < R; ++m) s += k2a[t + TPP * m] * (double)abs2(v[m]);
-      s = block_sum(s, red);
-      if (tid == 0) a.partial[f * gridDim.x + blockIdx.x] = s;
-    }
-  } else if constexpr (MODE == PASS_POT_SUM) {
-    cx<T> zv[R];
-    load(reinterpret_cast<const cx<T>*>(a.z) + pair * a.ncell, zv);
-    if (a.pot_green) {
-      const double* __restrict__ k2a = a.k2[a.axis];
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const double k2 = k2a[t + TPP * m];
-        zv[m] = mul_d(zv[m], (k2 == 0.0) ? 0.0 : a.green / k2);
-      }
-    }
-    fft_pencil<T, N, true, SW>(zv, lds, t, twd);
-    for (int k = 0; k < 2; ++k) {
-      const int64_t f = 2 * pair + k;
-      if (f >= a.nfield) break;
-      cx<T> v[R];
-      load(field_ptr<T>(a, f), v);
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < R; ++m) s += (double)(k == 0 ? zv[m].re : zv[m].im) * (double)abs2(v[m]);
-      s = block_sum(s, red);
-      if (tid == 0) a.partial[f * gridDim.x + blockIdx.x] = s;
-    }
-  }
+  pass_body<T, N, MODE, ROWS>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 template <class T, int N, bool ROWS>
@@ -269,42 +67,44 @@ static hipError_t launch_pass_tn(int mode, const PassArgs& a, hipStream_t s, int
 template <class T>
 static hipError_t launch_pass_t(int mode, const PassArgs& a, hipStream_t s, int ny) {
   switch (a.n[a.axis]) {
-    case 16: return launch_pass_tn<T, 16>(mode, a, s, ny);
-    case 32: return launch_pass_tn<T, 32>(mode, a, s, ny);
-    case 64: return launch_pass_tn<T, 64>(mode, a, s, ny);
-    case 128: return launch_pass_tn<T, 128>(mode, a, s, ny);
-    case 256: return launch_pass_tn<T, 256>(mode, a, s, ny);
-    case 512: return launch_pass_tn<T, 512>(mode, a, s, ny);
-    case 1024: return launch_pass_tn<T, 1024>(mode, a, s, ny);
+#define TW_CASE(L) \
+  case L: return launch_pass_tn<T, L>(mode, a, s, ny);
+    TW_PASS_LENGTHS(TW_CASE)
+#undef TW_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
 bool pass_length_supported(int n) {
-  return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+  switch (n) {
+#define TW_CASE(L) case L:
+    TW_PASS_LENGTHS(TW_CASE)
+#undef TW_CASE
+    return true;
+    default: return false;
+  }
 }
 
-int pass_pencils_per_group(int n, bool fp32, bool rows) {
+int pass_pencils_per_group(int n, bool fp32, bool rows, int variant) {
   auto pick = [&](auto tag, auto r) -> int {
     using T = decltype(tag);
     constexpr bool RW = decltype(r)::value;
     switch (n) {
-      case 16: return pencils_per_group<T, 16, RW>();
-      case 32: return pencils_per_group<T, 32, RW>();
-      case 64: return pencils_per_group<T, 64, RW>();
-      case 128: return pencils_per_group<T, 128, RW>();
-      case 256: return pencils_per_group<T, 256, RW>();
-      case 512: return pencils_per_group<T, 512, RW>();
-      case 1024: return pencils_per_group<T, 1024, RW>();
+#define TW_CASE(L) \
+  case L: return pencils_per_group<T, L, RW>();
+      TW_PASS_LENGTHS(TW_CASE)
+#undef TW_CASE
       default: return 0;
     }
   };
+  if (!rows && variant == 1) return cols_pencils_per_group(n, fp32);
   if (fp32) return rows ? pick(float{}, std::true_type{}) : pick(float{}, std::false_type{});
   return rows ? pick(double{}, std::true_type{}) : pick(double{}, std::false_type{});
 }
 
 hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int ny) {
   if (ny <= 0) return hipSuccess;
+  if (a.stride != 1 && a.variant == 1) return launch_pass_cols(P, mode, a, s, ny);
   return P.fp32 ? launch_pass_t<float>(mode, a, s, ny) : launch_pass_t<double>(mode, a, s, ny);
 }
 
@@ -338,6 +138,8 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
   cx<T>* fp = !active ? nullptr
               : (f < n_real ? reinterpret_cast<cx<T>*>(psi) + f * N : reinterpret_cast<cx<T>*>(psi_cl));
   const double mean = (active && rho_mean) ? rho_mean[f] : 0.0;
+  TwiddleCache<T, N> tc;
+  tc.load(twd, t);
 
   cx<T> v[R];
 #pragma unroll
@@ -349,10 +151,10 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
     g[m] = (kk == 0.0) ? 0.0 : green / kk;
   }
   auto drift = [&](const cx<double>* ph) {
-    fft_pencil<T, N, false, true>(v, lds, t, twd);
+    fft_pencil<T, N, false, true>(v, lds, t, tc);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
-    fft_pencil<T, N, true, true>(v, lds, t, twd);
+    fft_pencil<T, N, true, true>(v, lds, t, tc);
   };
 
   drift(ph_half);
@@ -360,10 +162,10 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
     cx<T> zv[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) zv[m] = {(T)(m_tot * (double)abs2(v[m]) - mean), (T)0};
-    fft_pencil<T, N, false, true>(zv, lds, t, twd);
+    fft_pencil<T, N, false, true>(zv, lds, t, tc);
 #pragma unroll
     for (int m = 0; m < R; ++m) zv[m] = mul_d(zv[m], g[m]);
-    fft_pencil<T, N, true, true>(zv, lds, t, twd);
+    fft_pencil<T, N, true, true>(zv, lds, t, tc);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], expmi<T>(kick * (double)zv[m].re));
     drift(s + 1 < nsteps ? ph_full : ph_half);
@@ -392,19 +194,15 @@ template <class T>
 static hipError_t launch_step1d_t(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                                   const void* ph_half, const void* ph_full, double kick, hipStream_t s) {
   switch (P.n[0]) {
-    case 8: return launch_step1d_tn<T, 8>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 16: return launch_step1d_tn<T, 16>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 32: return launch_step1d_tn<T, 32>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 64: return launch_step1d_tn<T, 64>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 128: return launch_step1d_tn<T, 128>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 256: return launch_step1d_tn<T, 256>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 512: return launch_step1d_tn<T, 512>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
-    case 1024: return launch_step1d_tn<T, 1024>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+#define TW_CASE(L) \
+  case L: return launch_step1d_tn<T, L>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s);
+    TW_STEP1D_LENGTHS(TW_CASE)
+#undef TW_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
-bool step1d_length_supported(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+bool step1d_length_supported(int n) { return n == 8 || pass_length_supported(n); }
 
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* ph_half, const void* ph_full, double kick, hipStream_t s) {

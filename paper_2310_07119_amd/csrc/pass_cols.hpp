@@ -1,0 +1,281 @@
+// Passes along a strided axis (y or z): the same per-pencil work as the row
+// passes (drift, density transform, Poisson transforms, kick), organised so
+// that global memory is touched in coalesced tiles and every FFT exchange stays
+// inside one wavefront.
+//
+// A workgroup of 4 wavefronts owns C adjacent pencils (C >= 64 bytes of
+// contiguous elements per row). Each field is moved as a tile: every thread
+// loads K elements row-by-row (consecutive lanes -> consecutive pencils, so a
+// load instruction reads whole 64-byte segments) into a padded LDS tile laid
+// out pencil-major; after one workgroup barrier each wavefront reads whole
+// pencils out of the tile in the FFT's natural layout, transforms them with
+// wavefront-local exchanges inside that pencil's own slot, and writes them
+// back; a second barrier and a coalesced tile store follow. The next tile's
+// global loads are issued before the current tile's transforms so that memory
+// latency overlaps the arithmetic.
+#pragma once
+#include "pass_common.hpp"
+
+namespace tw {
+
+template <class T, int N>
+struct ColsCfg {
+  static constexpr int TPP = fft_threads(N);
+  static constexpr int R = N / TPP;
+  static constexpr int PPW = 64 / TPP;                       // pencils per wavefront per round
+  static constexpr int COAL = 64 / (int)(2 * sizeof(T));     // pencils per 64 contiguous bytes
+  // at least 4 wavefronts; up to 8 so that one round covers the tile
+  static constexpr int WAVES = (COAL / PPW) > 4 ? ((COAL / PPW) < 8 ? (COAL / PPW) : 8) : 4;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int C = COAL > WAVES * PPW ? COAL : WAVES * PPW;
+  static constexpr int ROUNDS = C / (WAVES * PPW);
+  static constexpr int LS = fft_lds_stride(N);
+  static constexpr int K = C * N / THREADS;                  // tile elements per thread
+  static constexpr int ROWSTEP = THREADS / C;
+  static constexpr size_t LDS = (size_t)C * LS * 2 * sizeof(T) + 16 * sizeof(double);
+  static_assert(THREADS % C == 0 && (C * N) % THREADS == 0, "tile shape");
+};
+
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One workgroup of a strided pass: x-block bx of nbx, pair slot by (relative to a.pair0).
+template <class T, int N, int MODE>
+__device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsigned nbx, int64_t by) {
+  using Cfg = ColsCfg<T, N>;
+  constexpr int TPP = Cfg::TPP, R = Cfg::R, C = Cfg::C, K = Cfg::K, LS = Cfg::LS;
+  constexpr int ROUNDS = Cfg::ROUNDS, ROWSTEP = Cfg::ROWSTEP, PPW = Cfg::PPW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tile = reinterpret_cast<cx<T>*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * LS * sizeof(cx<T>));
+
+  const int tid = threadIdx.x;
+  const unsigned grp = xcd_pair_remap(bx, nbx);
+  const int64_t npencils = a.ncell / N;
+  const int64_t stride = a.stride;
+  const int64_t pair = a.pair0 + by;
+  const int64_t fA = 2 * pair, fB = 2 * pair + 1;
+  const bool hasB = fB < a.nfield;
+
+  // tile-movement role: pencil cl of the tile, rows r0 + ROWSTEP k
+  const int cl = tid % C;
+  const int r0 = tid / C;
+  const int64_t pl = (int64_t)grp * C + cl;
+  const bool act_l = pl < npencils;
+  const int64_t pll = act_l ? pl : 0;
+  const int64_t base_l = (pll % stride) + (pll / stride) * stride * N;
+  // compute role: wavefront w, lane -> pencil slot and thread-in-pencil
+  const int w = tid >> 6, lane = tid & 63;
+  const int t = lane % TPP;
+
+  auto gload = [&](const cx<T>* f, cx<T> (&st)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      st[k] = act_l ? f[base_l + (int64_t)(r0 + ROWSTEP * k) * stride] : cx<T>{(T)0, (T)0};
+  };
+  auto tile_put = [&](const cx<T> (&st)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) tile[cl * LS + lds_pad(r0 + ROWSTEP * k)] = st[k];
+  };
+  auto tile_store = [&](cx<T>* f) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const cx<T> v = tile[cl * LS + lds_pad(r0 + ROWSTEP * k)];
+      if (act_l) f[base_l + (int64_t)(r0 + ROWSTEP * k) * stride] = v;
+    }
+  };
+  auto slot = [&](int q) { return (q * Cfg::WAVES + w) * PPW + lane / TPP; };
+  auto pencil_get = [&](int q, cx<T> (&v)[R]) {
+    const cx<T>* src = tile + slot(q) * LS;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = src[lds_pad(t + TPP * m)];
+  };
+  auto pencil_put = [&](int q, const cx<T> (&v)[R]) {
+    cx<T>* dst = tile + slot(q) * LS;
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[lds_pad(t + TPP * m)] = v[m];
+  };
+  // pencil index (global) held by slot q, for k-space coordinates
+  auto pencil_base = [&](int q) -> int64_t {
+    const int64_t p = (int64_t)grp * C + slot(q);
+    const int64_t pp = p < npencils ? p : 0;
+    return (pp % stride) + (pp / stride) * stride * N;
+  };
+
+  TwiddleCache<T, N> tc;
+  tc.load(reinterpret_cast<const cx<T>*>(a.twd), t);
+  auto fwd = [&](int q, cx<T> (&v)[R]) { fft_pencil<T, N, false, true>(v, tile + slot(q) * LS, t, tc); };
+  auto inv = [&](int q, cx<T> (&v)[R]) { fft_pencil<T, N, true, true>(v, tile + slot(q) * LS, t, tc); };
+  auto drift = [&](int q, cx<T> (&v)[R]) {
+    fwd(q, v);
+    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
+    inv(q, v);
+  };
+  cx<T>* zp = reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell;
+  cx<T> st[K];
+
+  if constexpr (MODE == PASS_DRIFT || MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
+    T rho[2][ROUNDS][R];
+    gload(field_ptr<T>(a, fA), st);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = k == 0 ? fA : fB;
+      if (k == 1 && !hasB) {
+#pragma unroll
+        for (int q = 0; q < ROUNDS; ++q)
+#pragma unroll
+          for (int m = 0; m < R; ++m) rho[1][q][m] = (T)0;
+        break;
+      }
+      tile_put(st);
+      lds_barrier();
+      if (k == 0 && hasB) gload(field_ptr<T>(a, fB), st);
+      const double mean = a.rho_mean ? a.rho_mean[f] : 0.0;
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) {
+        cx<T> v[R];
+        pencil_get(q, v);
+        if constexpr (MODE != PASS_RHO) {
+          drift(q, v);
+          pencil_put(q, v);
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) rho[k][q][m] = (T)(a.m_tot * (double)abs2(v[m]) - mean);
+      }
+      lds_barrier();
+      if constexpr (MODE != PASS_RHO) {
+        tile_store(field_ptr<T>(a, f));
+        lds_barrier();
+      }
+    }
+    if constexpr (MODE != PASS_DRIFT) {
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) {
+        cx<T> v[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = {rho[0][q][m], rho[1][q][m]};
+        fwd(q, v);
+        pencil_put(q, v);
+      }
+      lds_barrier();
+      tile_store(zp);
+    }
+  } else if constexpr (MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON) {
+    gload(zp, st);
+    tile_put(st);
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < ROUNDS; ++q) {
+      cx<T> v[R];
+      pencil_get(q, v);
+      if constexpr (MODE == PASS_ZINV) {
+        inv(q, v);
+      } else {
+        fwd(q, v);
+      }
+      if constexpr (MODE == PASS_ZPOISSON) {
+        const int64_t b = pencil_base(q);
+        const int64_t co[3] = {b % a.n[0], (b / a.n[0]) % a.n[1], b / ((int64_t)a.n[0] * a.n[1])};
+        double k2o = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (d != a.axis) k2o += a.k2[d][co[d]];
+        const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const double k2 = k2o + k2a[t + TPP * m];
+          v[m] = mul_d(v[m], (k2 == 0.0) ? 0.0 : a.green / k2);
+        }
+        inv(q, v);
+      }
+      pencil_put(q, v);
+    }
+    lds_barrier();
+    tile_store(zp);
+  } else if constexpr (MODE == PASS_KICK_DRIFT || MODE == PASS_POT_SUM) {
+    cx<T> V[ROUNDS][R];
+    gload(zp, st);
+    tile_put(st);
+    lds_barrier();
+    gload(field_ptr<T>(a, fA), st);
+#pragma unroll
+    for (int q = 0; q < ROUNDS; ++q) {
+      pencil_get(q, V[q]);
+      if constexpr (MODE == PASS_POT_SUM) {
+        if (a.pot_green) {
+          const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+          for (int m = 0; m < R; ++m) {
+            const double k2 = k2a[t + TPP * m];
+            V[q][m] = mul_d(V[q][m], (k2 == 0.0) ? 0.0 : a.green / k2);
+          }
+        }
+      }
+      inv(q, V[q]);
+    }
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = k == 0 ? fA : fB;
+      if (k == 1 && !hasB) break;
+      lds_barrier();
+      tile_put(st);
+      lds_barrier();
+      if (k == 0 && hasB) gload(field_ptr<T>(a, fB), st);
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) {
+        cx<T> v[R];
+        pencil_get(q, v);
+        if constexpr (MODE == PASS_KICK_DRIFT) {
+#pragma unroll
+          for (int m = 0; m < R; ++m) {
+            v[m] = cmul(v[m], expmi<T>(a.kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
+            __builtin_amdgcn_sched_barrier(0);  // one sincos at a time: bounds live registers
+          }
+          drift(q, v);
+          pencil_put(q, v);
+        } else {
+          const bool on = ((int64_t)grp * C + slot(q)) < npencils;
+#pragma unroll
+          for (int m = 0; m < R; ++m)
+            s += on ? (double)(k == 0 ? V[q][m].re : V[q][m].im) * (double)abs2(v[m]) : 0.0;
+        }
+      }
+      if constexpr (MODE == PASS_KICK_DRIFT) {
+        lds_barrier();
+        tile_store(field_ptr<T>(a, f));
+      } else {
+        s = block_sum(s, red);
+        if (tid == 0) a.partial[f * nbx + grp] = s;
+      }
+    }
+  } else if constexpr (MODE == PASS_KIN_SUM) {
+    const double* __restrict__ k2a = a.k2[a.axis];
+    gload(field_ptr<T>(a, fA), st);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t f = k == 0 ? fA : fB;
+      if (k == 1 && !hasB) break;
+      if (k == 1) lds_barrier();
+      tile_put(st);
+      lds_barrier();
+      if (k == 0 && hasB) gload(field_ptr<T>(a, fB), st);
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) {
+        cx<T> v[R];
+        pencil_get(q, v);
+        fwd(q, v);
+        const bool on = ((int64_t)grp * C + slot(q)) < npencils;
+#pragma unroll
+        for (int m = 0; m < R; ++m) s += on ? k2a[t + TPP * m] * (double)abs2(v[m]) : 0.0;
+      }
+      s = block_sum(s, red);
+      if (tid == 0) a.partial[f * nbx + grp] = s;
+    }
+  }
+}
+
+}  // namespace tw

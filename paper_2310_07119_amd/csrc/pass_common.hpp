@@ -1,0 +1,69 @@
+// Device helpers shared by the row-pass and strided-pass kernels.
+#pragma once
+#include "common.hpp"
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace tw {
+
+// Pencils per workgroup. Row passes (stride 1): 4 wavefronts, every pencil
+// inside one wavefront, so the FFT exchanges are wavefront-local. Strided passes:
+// C adjacent pencils with lane = c + C t, so each global access instruction
+// covers C contiguous elements (64 bytes: 4 complex128 or 8 complex64); the
+// exchanges are workgroup-wide. Two workgroups share each 128-byte line; the
+// block remap below places them on the same XCD.
+template <class T, int N, bool ROWS>
+__host__ __device__ constexpr int pencils_per_group() {
+  constexpr int TPP = fft_threads(N);
+  if constexpr (ROWS) {
+    return 4 * (64 / TPP);
+  } else {
+    int c = 256 / TPP;
+    const int coal = 64 / (int)(2 * sizeof(T));
+    if (c < coal) c = coal;
+    while (c > 1 && c * TPP > 512) c /= 2;
+    while (c > 1 && (long)c * fft_lds_stride(N) * 2 * (long)sizeof(T) > 96 * 1024) c /= 2;
+    return c;
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (id mod 8), each with
+// its own L2. Remap so that logical groups 2k and 2k+1 (which share cache lines
+// on strided passes) run on the same XCD: physical 16q + 8h + x -> logical
+// 16q + 2x + h. Grids that are not a multiple of 16 keep the identity.
+__device__ __forceinline__ unsigned xcd_pair_remap(unsigned b, unsigned nb) {
+  if (nb % 16 != 0) return b;
+  const unsigned q = b >> 4, h = (b >> 3) & 1, x = b & 7;
+  return (q << 4) | (x << 1) | h;
+}
+template <class T, int N, bool ROWS>
+__host__ __device__ constexpr int pass_threads() {
+  return pencils_per_group<T, N, ROWS>() * fft_threads(N);
+}
+template <class T, int N, bool ROWS>
+__host__ __device__ constexpr size_t pass_lds_bytes() {
+  return (size_t)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 2 * sizeof(T) + 16 * sizeof(double);
+}
+
+template <class T>
+__device__ __forceinline__ cx<T>* field_ptr(const PassArgs& a, int64_t f) {
+  return f < a.n_real ? reinterpret_cast<cx<T>*>(a.psi) + f * a.ncell : reinterpret_cast<cx<T>*>(a.psi_cl);
+}
+
+// Sum of `x` over the workgroup; result valid in thread 0. `red` holds one
+// double per wave.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += red[w];
+  }
+  return s;
+}
+
+}  // namespace tw

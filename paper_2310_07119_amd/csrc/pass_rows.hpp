@@ -1,0 +1,189 @@
+// Body of one workgroup of a pencil pass (row passes, and the interleaved
+// organisation of strided passes); kernels_step.hip wraps it in kernels and the
+// batched launcher calls it for every size class.
+#pragma once
+#include "pass_common.hpp"
+
+namespace tw {
+
+// One workgroup of a pass: x-block bx of nbx, pair slot by (relative to a.pair0).
+template <class T, int N, int MODE, bool ROWS>
+__device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsigned nbx, int64_t by) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int R = N / TPP;
+  constexpr int C = pencils_per_group<T, N, ROWS>();
+  constexpr bool SW = ROWS;  // wavefront-local exchanges
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * fft_lds_stride(N) * sizeof(cx<T>));
+
+  const int tid = threadIdx.x;
+  const int c = ROWS ? tid / TPP : tid % C;
+  const int t = ROWS ? tid % TPP : tid / C;
+  cx<T>* lds = lds_all + c * fft_lds_stride(N);
+  const int64_t npencils = a.ncell / N;
+  const unsigned grp = ROWS ? bx : xcd_pair_remap(bx, nbx);
+  const int64_t p = (int64_t)grp * C + c;
+  const bool active = p < npencils;
+  const int64_t pp = active ? p : 0;
+  const int64_t base = (pp % a.stride) + (pp / a.stride) * a.stride * N;
+  const int64_t stride = a.stride;
+  const int64_t pair = a.pair0 + by;
+  const int64_t fA = 2 * pair, fB = 2 * pair + 1;
+  const bool hasB = fB < a.nfield;
+
+  auto load = [&](const cx<T>* f, cx<T> (&v)[R]) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = active ? f[base + (int64_t)(t + TPP * m) * stride] : cx<T>{(T)0, (T)0};
+  };
+  auto store = [&](cx<T>* f, const cx<T> (&v)[R]) {
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) f[base + (int64_t)(t + TPP * m) * stride] = v[m];
+    }
+  };
+  auto zero = [&](cx<T> (&v)[R]) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cx<T>{(T)0, (T)0};
+  };
+  cx<T>* zp = reinterpret_cast<cx<T>*>(a.z) + pair * a.ncell;
+
+  // Issue every global load of the pass before the first transform: the
+  // exchanges carry fences that the compiler does not move loads across, so
+  // loads placed later would each wait a full memory latency.
+  cx<T> va[R], vb[R], zv[R];
+  constexpr bool LOAD_PSI = MODE == PASS_DRIFT || MODE == PASS_DRIFT_RHO || MODE == PASS_RHO ||
+                            MODE == PASS_KICK_DRIFT || MODE == PASS_KIN_SUM || MODE == PASS_POT_SUM;
+  constexpr bool LOAD_Z = MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON ||
+                          MODE == PASS_KICK_DRIFT || MODE == PASS_POT_SUM;
+  if constexpr (LOAD_Z) load(zp, zv);
+  if constexpr (LOAD_PSI) {
+    load(field_ptr<T>(a, fA), va);
+    if (hasB) load(field_ptr<T>(a, fB), vb);
+    else zero(vb);
+  }
+  TwiddleCache<T, N> tc;
+  tc.load(reinterpret_cast<const cx<T>*>(a.twd), t);
+
+  auto drift = [&](cx<T> (&v)[R]) {
+    fft_pencil<T, N, false, SW>(v, lds, t, tc);
+    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
+    fft_pencil<T, N, true, SW>(v, lds, t, tc);
+  };
+  auto density = [&](const cx<T> (&v)[R], int64_t f, double (&rho)[R]) {
+    const double mean = a.rho_mean ? a.rho_mean[f] : 0.0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) rho[m] = a.m_tot * (double)abs2(v[m]) - mean;
+  };
+
+  if constexpr (MODE == PASS_DRIFT) {
+    drift(va);
+    store(field_ptr<T>(a, fA), va);
+    if (hasB) {
+      drift(vb);
+      store(field_ptr<T>(a, fB), vb);
+    }
+  } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
+    if constexpr (MODE == PASS_DRIFT_RHO) {
+      drift(va);
+      store(field_ptr<T>(a, fA), va);
+      if (hasB) {
+        drift(vb);
+        store(field_ptr<T>(a, fB), vb);
+      }
+    }
+    double ra[R], rb[R];
+    density(va, fA, ra);
+    if (hasB) {
+      density(vb, fB, rb);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) rb[m] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) zv[m] = {(T)ra[m], (T)rb[m]};
+    fft_pencil<T, N, false, SW>(zv, lds, t, tc);
+    store(zp, zv);
+  } else if constexpr (MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON) {
+    if constexpr (MODE == PASS_ZINV) {
+      fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+    } else {
+      fft_pencil<T, N, false, SW>(zv, lds, t, tc);
+    }
+    if constexpr (MODE == PASS_ZPOISSON) {
+      const int64_t x0 = base % a.n[0];
+      const int64_t y0 = (base / a.n[0]) % a.n[1];
+      const int64_t z0 = base / ((int64_t)a.n[0] * a.n[1]);
+      const int64_t co[3] = {x0, y0, z0};
+      double k2o = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (d != a.axis) k2o += a.k2[d][co[d]];
+      const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double k2 = k2o + k2a[t + TPP * m];
+        const double g = (k2 == 0.0) ? 0.0 : a.green / k2;
+        zv[m] = mul_d(zv[m], g);
+      }
+      fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+    }
+    store(zp, zv);
+  } else if constexpr (MODE == PASS_KICK_DRIFT) {
+    fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      va[m] = cmul(va[m], expmi<T>(a.kick * (double)zv[m].re));
+      __builtin_amdgcn_sched_barrier(0);  // one sincos at a time: bounds live registers
+    }
+    drift(va);
+    store(field_ptr<T>(a, fA), va);
+    if (hasB) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        vb[m] = cmul(vb[m], expmi<T>(a.kick * (double)zv[m].im));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      drift(vb);
+      store(field_ptr<T>(a, fB), vb);
+    }
+  } else if constexpr (MODE == PASS_KIN_SUM) {
+    const double* __restrict__ k2a = a.k2[a.axis];
+    for (int k = 0; k < 2; ++k) {
+      if (k == 1 && !hasB) break;
+      cx<T>* v = k == 0 ? va : vb;
+      cx<T> w[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) w[m] = v[m];
+      fft_pencil<T, N, false, SW>(w, lds, t, tc);
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) s += k2a[t + TPP * m] * (double)abs2(w[m]);
+      s = block_sum(s, red);
+      if (tid == 0) a.partial[(2 * pair + k) * nbx + grp] = s;
+    }
+  } else if constexpr (MODE == PASS_POT_SUM) {
+    if (a.pot_green) {
+      const double* __restrict__ k2a = a.k2[a.axis];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double k2 = k2a[t + TPP * m];
+        zv[m] = mul_d(zv[m], (k2 == 0.0) ? 0.0 : a.green / k2);
+      }
+    }
+    fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+    for (int k = 0; k < 2; ++k) {
+      if (k == 1 && !hasB) break;
+      const cx<T>* v = k == 0 ? va : vb;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) s += (double)(k == 0 ? zv[m].re : zv[m].im) * (double)abs2(v[m]);
+      s = block_sum(s, red);
+      if (tid == 0) a.partial[(2 * pair + k) * nbx + grp] = s;
+    }
+  }
+}
+
+}  // namespace tw

@@ -24,7 +24,7 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
 
 # Exported entry points and their argument types (mirrors include/tw.h).
 EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_moments",
-           "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
+           "tw_plan_autotune", "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
 NUM_KERNEL_KINDS = 16
 
 
@@ -59,6 +59,7 @@ def load_library(path=LIB_PATH):
     lib.tw_sample.argtypes = [vp, vp, u64, i64, vp, vp]
     lib.tw_step.argtypes = [vp, vp, vp, i64, dbl, vp]
     lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
+    lib.tw_plan_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.tw_plan_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.tw_plan_get_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -182,6 +183,12 @@ class Plan:
         _check(self._lib.tw_step(self._h, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
                "tw_step")
         return psi
+
+    def autotune(self):
+        """Measure both strided-pass organisations and keep the faster (tw_plan_autotune)."""
+        v = ctypes.c_int32(-1)
+        _check(self._lib.tw_plan_autotune(self._h, ctypes.byref(v), _stream()), "tw_plan_autotune")
+        return int(v.value)
 
     def set_profiling(self, enable=True):
         """Bracket every kernel launch with HIP events on its stream (tw_plan_set_profiling)."""

@@ -32,10 +32,14 @@ def _cuda():
         pytest.skip("no GPU")
 
 
+@pytest.mark.parametrize("variant", ["0", "1"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", CASES, ids=_ids)
-def test_sample_step_moments_vs_oracle(case, precision):
+def test_sample_step_moments_vs_oracle(case, precision, variant, monkeypatch):
     n, nr, nsteps, dt, hbar, G, m_tot, n_tot = case
+    if len(n) == 1 and variant == "1":
+        pytest.skip("1D has no strided passes")
+    monkeypatch.setenv("TW_COLS_VARIANT", variant)
     p = Problem(n=n, hbar_m=hbar, G=G, m_tot=m_tot, n_tot=n_tot, n_real=nr, precision=precision)
     psi_cl = inputs.lognormal_field(n, p.box, kcut=min(n) // 4, seed=1)
     seed = 1234567
@@ -76,6 +80,22 @@ def test_zero_steps_and_no_classical(precision):
     ref = tw.moments(prob, g["psi0"].astype(np.complex128), p.n_tot)
     assert abs(g["mom"]["Q_raw"] - ref["Q_raw"]) < 1e-10 * ref["Q_raw"]
     assert g["mom"]["dev_rho_L1"] == 0.0
+
+
+def test_autotune_picks_a_variant_and_caches_it(tmp_path, monkeypatch):
+    from paper_2310_07119_amd import Plan
+    monkeypatch.setenv("TW_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.delenv("TW_COLS_VARIANT", raising=False)
+    p = Problem(n=(64, 128), n_real=9, n_tot=1e4, precision="fp32")
+    v = Plan(p).autotune()
+    assert v in (0, 1)
+    text = (tmp_path / "tune.json").read_text()
+    import json
+    entry = list(json.loads(text).values())[0]
+    assert entry["cols_variant"] == v and len(entry["us"]) == 2
+    # a second plan of the same shape reads the cache (same choice, no new entry)
+    Plan(Problem(n=(64, 128), n_real=9, n_tot=1e4, precision="fp32")).autotune()
+    assert len(json.loads((tmp_path / "tune.json").read_text())) == 1
 
 
 def test_nonfinite_realization_is_counted():
