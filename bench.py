@@ -107,6 +107,58 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     return res
 
 
+def run_batched(steps, warmup, seed=7):
+    """The three-size 3D soliton ensemble (FP32 split) advanced as one batch:
+    every pass is one grouped launch over all classes and the K steps are one
+    HIP graph launch. Also times the same classes advanced one plan at a time."""
+    import torch
+    from paper_2310_07119_amd import Batch, Plan, Problem, inputs
+
+    wl = inputs.WORKLOADS["3d_batched_soliton"]
+    probs = [Problem(n=n, box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                     n_tot=wl["occupation"] * n[0] * n[1] * n[2], n_real=wl["n_real"], precision="fp32")
+             for n in wl["classes"]]
+    batch = Batch(probs)
+    variant, mode = batch.autotune()
+    psis = []
+    for p, plan in zip(probs, batch.plans):
+        cl = torch.from_numpy(inputs.soliton_3d(p.n, p.box, core=0.1)).cuda()
+        psis.append(plan.sample(cl, seed))
+    dt = wl["dt"]
+    work = sum(p.n_real * p.ncell for p in probs) * steps
+    batch.step(psis, steps, dt)          # capture + warm
+    for _ in range(max(warmup, 0)):
+        batch.step(psis, steps, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(psis, steps, dt)          # one graph launch
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    singles = [Plan(p) for p in probs]
+    for pl in singles:
+        pl.autotune()
+    for pl, x in zip(singles, psis):
+        pl.step(x, steps, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, x in zip(singles, psis):
+        pl.step(x, steps, dt)
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    out = {"workload": "3d_batched_soliton", "classes": [list(p.n) for p in probs],
+           "n_real_per_class": wl["n_real"], "precision": "fp32", "steps": steps,
+           "value": work / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
+           "unbatched_value": work / el1, "speedup_vs_unbatched": el1 / el, "strided_pass_variant": variant,
+           "batch_mode": ["grouped launches", "per-class graph branches"][mode],
+           "launch": "one hipGraph launch for all classes and all steps"}
+    batch.close()
+    for pl in singles:
+        pl.close()
+    del psis
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, budget_s=15.0, n_sample_real=4, seed=20231007):
     """The oracle as it stands, on a bounded sample: n_sample_real realizations of
     the full grid, as many steps as fit in about budget_s seconds."""
@@ -144,6 +196,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -183,6 +236,9 @@ def main():
             "err_vs_fp64": {k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")},
         }
         log(f"fp32: {r32['value']:.4e}, errors {out['fp32_split']['err_vs_fp64']}")
+    if not args.no_batched:
+        out["batched"] = run_batched(max(args.steps // 2, 1), 1)
+        log(f"batched: {out['batched']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
         log(f"cpu oracle: {out['cpu_baseline']}")

@@ -142,6 +142,44 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
  * TW_COLS_VARIANT=0|1, read by tw_plan_create, forces a choice instead. */
 int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Ensembles of different grid sizes advanced together (the same method per
+ * size class). Every pass of a step is ONE launch covering all classes, and a
+ * whole tw_batch_step call is captured once into a HIP graph and replayed with
+ * a single graph launch while (nsteps, dt, field pointers) stay the same. */
+typedef struct tw_batch_s* tw_batch;
+
+/* problems[0..count-1], 1 <= count <= 4: one size class each, all with the same
+ * dim (2 or 3) and precision; grid lengths 16, 24, 32, 48, 64, 96 or 128.
+ * Creates one plan per class (owned by the batch). Synchronous. */
+int tw_batch_create(const tw_problem* problems, int32_t count, tw_batch* out);
+
+/* The plan of class `index`, owned by the batch (valid until tw_batch_destroy);
+ * use it with tw_sample and tw_moments. Do not destroy it. */
+int tw_batch_plan(tw_batch batch, int32_t index, tw_plan* out);
+
+/* Tune the batch on scratch buffers (allocated and freed here): the
+ * strided-pass organisation of the grouped launches (timed on up to 8 pairs
+ * per class), each class plan (tw_plan_autotune), and the batching mode, timed
+ * on full-size scratch ensembles: 0 = one grouped launch per pass for all
+ * classes, 1 = one kernel chain per class, the chains running as parallel
+ * branches of the graph. Choices are cached under a key listing every class
+ * (TW_BATCH_MODE=0|1 and TW_COLS_VARIANT=0|1 force them instead). Synchronous.
+ * *variant_out and *mode_out (either may be NULL) receive the choices. */
+int tw_batch_autotune(tw_batch batch, int32_t* variant_out, int32_t* mode_out, void* stream);
+
+/* tw_step for every class: psi[c] (and psi_classical[c] if the array is
+ * non-NULL; entries may be NULL) are class c's fields. Captures the launch
+ * sequence into a graph on first use with these arguments (the capture runs on
+ * streams owned by the batch), then launches the graph on `stream`. Results
+ * equal those of tw_step on the class plans with the same strided-pass
+ * organisation. */
+int tw_batch_step(tw_batch batch, void* const* psi, void* const* psi_classical, int64_t nsteps, double dt,
+                  void* stream);
+
+/* Waits for the device, releases graphs, plans and workspace. NULL is a no-op. */
+int tw_batch_destroy(tw_batch batch);
+
 /* Kernel timing for measurement tools (not needed for the method itself).
  * When enabled, every kernel launched by tw_sample / tw_step / tw_moments on
  * this plan is bracketed by two HIP events recorded on the launch stream.

@@ -172,6 +172,75 @@ int64_t default_chunk_pairs(const Plan& P) { return P.npairs; }
 }  // namespace
 }  // namespace tw
 
+namespace tw {
+namespace {
+
+// The launch sequence of tw_step on stream s (arguments already validated).
+int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hipStream_t s) {
+  const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
+  const double h = 0.5 * dt;
+  // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
+  auto phase_slot = [&](int axis, int full) -> void* {
+    return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
+  };
+  for (int d = 0; d < P.dim; ++d) {
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
+  }
+  if (P.fp32)
+    TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
+  const double kick = dt / P.p.hbar_m;
+
+  if (P.dim == 1) {
+    TW_HIP(timed(P, KIND_STEP1D, s, [&] {
+      return launch_step1d(P, psi, psi_cl, nfield, nsteps, phase_slot(0, 0), phase_slot(0, 1), kick, s);
+    }));
+    return TW_OK;
+  }
+
+  PassArgs a = base_args(P, psi, psi_cl, nfield);
+  a.kick = kick;
+  a.rho_mean = P.fp32 ? P.rho_mean : nullptr;
+  const int D = P.dim;
+  const int64_t npairs = (nfield + 1) / 2;
+  const int64_t chunk = P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P);
+  // Realizations are independent: each chunk of pairs runs every step before
+  // the next chunk starts.
+  for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
+    const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
+    auto run = [&](int mode, int axis, const void* phase) { return pass(P, a, mode, axis, phase, s, c0, nc); };
+    int o[3] = {0, 1, 2};
+    // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
+    for (int i = D - 1; i >= 1; --i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
+    TW_HIP(run(PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0)));
+    for (int64_t st = 0; st < nsteps; ++st) {
+      const bool last = (st + 1 == nsteps);
+      const int full = last ? 0 : 1;
+      // rest of the forward transform of rho, Green's function, inverse (all but o[0])
+      for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_ZFWD, o[i], nullptr));
+      TW_HIP(run(PASS_ZPOISSON, o[D - 1], nullptr));
+      for (int i = D - 2; i >= 1; --i) TW_HIP(run(PASS_ZINV, o[i], nullptr));
+      // last inverse along o[0] -> V, kick, drift along o[0]
+      TW_HIP(run(PASS_KICK_DRIFT, o[0], phase_slot(o[0], full)));
+      if (!last) {
+        for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 1)));
+        TW_HIP(run(PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1)));
+        // reverse the axis order so the density transform just made is the first one
+        int r[3] = {0, 0, 0};
+        for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
+        for (int i = 0; i < D; ++i) o[i] = r[i];
+      } else {
+        for (int i = 1; i < D; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
+      }
+    }
+  }
+  return TW_OK;
+}
+
+
+}  // namespace
+}  // namespace tw
+
 using namespace tw;
 
 extern "C" {
@@ -347,65 +416,7 @@ int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, vo
   if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
   if (nsteps == 0) return TW_OK;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
-  const double h = 0.5 * dt;
-  // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
-  auto phase_slot = [&](int axis, int full) -> void* {
-    return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
-  };
-  for (int d = 0; d < P.dim; ++d) {
-    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
-    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
-  }
-  if (P.fp32)
-    TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
-  const double kick = dt / P.p.hbar_m;
-
-  if (P.dim == 1) {
-    TW_HIP(timed(P, KIND_STEP1D, s, [&] {
-      return launch_step1d(P, psi, psi_cl, nfield, nsteps, phase_slot(0, 0), phase_slot(0, 1), kick, s);
-    }));
-    return TW_OK;
-  }
-
-  PassArgs a = base_args(P, psi, psi_cl, nfield);
-  a.kick = kick;
-  a.rho_mean = P.fp32 ? P.rho_mean : nullptr;
-  const int D = P.dim;
-  const int64_t npairs = (nfield + 1) / 2;
-  const int64_t chunk = P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P);
-  // Realizations are independent: each chunk of pairs runs every step before
-  // the next chunk starts.
-  for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
-    const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
-    auto run = [&](int mode, int axis, const void* phase) { return pass(P, a, mode, axis, phase, s, c0, nc); };
-    int o[3] = {0, 1, 2};
-    // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
-    for (int i = D - 1; i >= 1; --i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
-    TW_HIP(run(PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0)));
-    for (int64_t st = 0; st < nsteps; ++st) {
-      const bool last = (st + 1 == nsteps);
-      const int full = last ? 0 : 1;
-      // rest of the forward transform of rho, Green's function, inverse (all but o[0])
-      for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_ZFWD, o[i], nullptr));
-      TW_HIP(run(PASS_ZPOISSON, o[D - 1], nullptr));
-      for (int i = D - 2; i >= 1; --i) TW_HIP(run(PASS_ZINV, o[i], nullptr));
-      // last inverse along o[0] -> V, kick, drift along o[0]
-      TW_HIP(run(PASS_KICK_DRIFT, o[0], phase_slot(o[0], full)));
-      if (!last) {
-        for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 1)));
-        TW_HIP(run(PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1)));
-        // reverse the axis order so the density transform just made is the first one
-        int r[3] = {0, 0, 0};
-        for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
-        for (int i = 0; i < D; ++i) o[i] = r[i];
-      } else {
-        for (int i = 1; i < D; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
-      }
-    }
-  }
-  return TW_OK;
+  return enqueue_step(P, psi, psi_cl, nsteps, dt, reinterpret_cast<hipStream_t>(stream));
 }
 
 int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_moments_out* out, void* stream) {
@@ -566,6 +577,394 @@ int tw_plan_get_profile(tw_plan plan, int32_t n_kinds, int64_t* launches, double
 const char* tw_kernel_kind_name(int32_t kind) {
   if (kind < 0 || kind >= KIND_COUNT) return "";
   return kKindNames[kind];
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+// Ensembles of several grid sizes advanced together: every pass of a step is
+// one grouped launch over all size classes, and a whole tw_batch_step call
+// (tables, density means, all steps) is captured once into a hipGraph and
+// replayed while the arguments stay the same.
+namespace tw {
+namespace {
+
+struct Batch {
+  int count = 0;
+  Plan* plans[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  bool fp32 = false;
+  int dim = 0;
+  int variant = 0;  // strided-pass organisation of the grouped launches
+  int mode = 0;     // 0: one grouped launch per pass; 1: one kernel chain per class, run as parallel graph branches
+  int tuned = 0;
+  hipStream_t cap = nullptr;
+  hipStream_t br[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t key_nsteps = -1;
+  double key_dt = 0.0;
+  void* key_psi[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  void* key_cl[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+void free_batch(Batch* B) {
+  if (!B) return;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  for (int c = 0; c < kMaxClasses; ++c) {
+    if (B->br[c]) (void)hipStreamDestroy(B->br[c]);
+    if (B->join[c]) (void)hipEventDestroy(B->join[c]);
+  }
+  if (B->fork) (void)hipEventDestroy(B->fork);
+  for (int c = 0; c < B->count; ++c) free_plan(B->plans[c]);
+  delete B;
+}
+
+std::string batch_key(const Batch& B) {
+  std::string k = tune_key(*B.plans[0]);
+  k = k.substr(0, k.find('|')) + "|batch";
+  for (int c = 0; c < B.count; ++c) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "|%dx%dx%d:%lld", B.plans[c]->n[0], B.plans[c]->n[1], B.plans[c]->n[2],
+             (long long)B.plans[c]->npairs);
+    k += buf;
+  }
+  return k + (B.fp32 ? "|fp32" : "|fp64");
+}
+
+void* phase_slot_of(const Plan& P, int axis, int full) {
+  return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
+}
+
+// One grouped pass over pairs [0, npairs_c) of every class c.
+hipError_t grouped(Batch& B, const PassArgs* base, int mode, int axis, int full, hipStream_t s,
+                   const int64_t* npairs = nullptr) {
+  GroupArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nclass = B.count;
+  for (int c = 0; c < B.count; ++c) {
+    const Plan& P = *B.plans[c];
+    PassArgs a = base[c];
+    a.axis = axis;
+    a.stride = axis_stride(P, axis);
+    a.twd = P.twd[axis];
+    a.phase = full >= 0 ? phase_slot_of(P, axis, full) : nullptr;
+    a.pair0 = 0;
+    if (npairs) a.nfield = std::min<int64_t>(a.nfield, 2 * npairs[c]);
+    a.variant = B.variant;
+    g.a[c] = a;
+  }
+  return launch_grouped(B.fp32, mode, g, B.variant, s);
+}
+
+// The launch sequence of tw_step for every class at once (all classes share
+// the dimension, so they share the pass sequence and axis order).
+int enqueue_batch(Batch& B, void* const* psi, void* const* psi_cl, int64_t nsteps, double dt, hipStream_t s) {
+  PassArgs base[kMaxClasses];
+  const double h = 0.5 * dt;
+  for (int c = 0; c < B.count; ++c) {
+    Plan& P = *B.plans[c];
+    const int64_t nfield = P.p.n_real + (psi_cl && psi_cl[c] ? 1 : 0);
+    for (int d = 0; d < P.dim; ++d) {
+      TW_HIP(launch_phase_table(P, d, h, phase_slot_of(P, d, 0), s));
+      TW_HIP(launch_phase_table(P, d, dt, phase_slot_of(P, d, 1), s));
+    }
+    if (P.fp32) TW_HIP(launch_field_mean(P, psi[c], psi_cl ? psi_cl[c] : nullptr, nfield, P.rho_mean, s));
+    base[c] = base_args(P, psi[c], psi_cl ? psi_cl[c] : nullptr, nfield);
+    base[c].kick = dt / P.p.hbar_m;
+    base[c].rho_mean = P.fp32 ? P.rho_mean : nullptr;
+  }
+  const int D = B.dim;
+  int o[3] = {0, 1, 2};
+  for (int i = D - 1; i >= 1; --i) TW_HIP(grouped(B, base, PASS_DRIFT, o[i], 0, s));
+  TW_HIP(grouped(B, base, PASS_DRIFT_RHO, o[0], 0, s));
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const bool last = (st + 1 == nsteps);
+    for (int i = 1; i < D - 1; ++i) TW_HIP(grouped(B, base, PASS_ZFWD, o[i], -1, s));
+    TW_HIP(grouped(B, base, PASS_ZPOISSON, o[D - 1], -1, s));
+    for (int i = D - 2; i >= 1; --i) TW_HIP(grouped(B, base, PASS_ZINV, o[i], -1, s));
+    TW_HIP(grouped(B, base, PASS_KICK_DRIFT, o[0], last ? 0 : 1, s));
+    if (!last) {
+      for (int i = 1; i < D - 1; ++i) TW_HIP(grouped(B, base, PASS_DRIFT, o[i], 1, s));
+      TW_HIP(grouped(B, base, PASS_DRIFT_RHO, o[D - 1], 1, s));
+      int r[3] = {0, 0, 0};
+      for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
+      for (int i = 0; i < D; ++i) o[i] = r[i];
+    } else {
+      for (int i = 1; i < D; ++i) TW_HIP(grouped(B, base, PASS_DRIFT, o[i], 0, s));
+    }
+  }
+  return TW_OK;
+}
+
+// Each class runs its own tw_step sequence (its own plan's strided-pass
+// organisation) on a stream of its own; forked from and joined back into s.
+int enqueue_batch_branches(Batch& B, void* const* psi, void* const* psi_cl, int64_t nsteps, double dt,
+                           hipStream_t s) {
+  TW_HIP(hipEventRecord(B.fork, s));
+  for (int c = 0; c < B.count; ++c) {
+    TW_HIP(hipStreamWaitEvent(B.br[c], B.fork, 0));
+    const int rc = enqueue_step(*B.plans[c], psi[c], psi_cl ? psi_cl[c] : nullptr, nsteps, dt, B.br[c]);
+    if (rc != TW_OK) return rc;
+    TW_HIP(hipEventRecord(B.join[c], B.br[c]));
+    TW_HIP(hipStreamWaitEvent(s, B.join[c], 0));
+  }
+  return TW_OK;
+}
+
+int enqueue_batch_mode(Batch& B, void* const* psi, void* const* psi_cl, int64_t nsteps, double dt, hipStream_t s) {
+  return B.mode == 1 ? enqueue_batch_branches(B, psi, psi_cl, nsteps, dt, s) : enqueue_batch(B, psi, psi_cl, nsteps, dt, s);
+}
+
+}  // namespace
+}  // namespace tw
+
+extern "C" {
+
+int tw_batch_create(const tw_problem* problems, int32_t count, tw_batch* out) {
+  if (!problems || !out) return fail(TW_EINVAL, "NULL problems or output pointer");
+  *out = nullptr;
+  if (count < 1 || count > kMaxClasses) return fail(TW_EINVAL, "count must be 1..%d", kMaxClasses);
+  for (int c = 0; c < count; ++c) {
+    const tw_problem& p = problems[c];
+    if (p.dim != problems[0].dim || p.precision != problems[0].precision)
+      return fail(TW_EINVAL, "all classes of a batch need the same dim and precision");
+    if (p.dim < 2) return fail(TW_EUNSUPPORTED, "batches are for D = 2 or 3 (1D plans run resident already)");
+    for (int d = 0; d < p.dim; ++d)
+      if (!batch_length_supported(p.n[d]))
+        return fail(TW_EUNSUPPORTED, "class %d: n[%d]=%d outside the batched lengths (16..128)", c, d, p.n[d]);
+  }
+  Batch* B = new (std::nothrow) Batch();
+  if (!B) return fail(TW_ENOMEM, "host allocation failed");
+  for (int c = 0; c < count; ++c) {
+    tw_plan pl = nullptr;
+    const int rc = tw_plan_create(&problems[c], &pl);
+    if (rc != TW_OK) {
+      free_batch(B);
+      return rc;
+    }
+    B->plans[c] = reinterpret_cast<Plan*>(pl);
+    B->count = c + 1;
+  }
+  B->fp32 = problems[0].precision == TW_FP32_SPLIT;
+  B->dim = problems[0].dim;
+  B->variant = B->fp32 ? 1 : 0;
+  const int v = tune_cache_lookup(batch_key(*B));
+  if (v >= 0) {
+    B->variant = v;
+    B->tuned = 1;
+  }
+  if (const char* env = getenv("TW_COLS_VARIANT")) {
+    const int ev = atoi(env);
+    if (ev == 0 || ev == 1) {
+      B->variant = ev;
+      B->tuned = 1;
+    }
+  }
+  const int m = tune_cache_lookup(batch_key(*B) + "|mode");
+  if (m >= 0) B->mode = m;
+  if (const char* env = getenv("TW_BATCH_MODE")) {
+    const int em = atoi(env);
+    if (em == 0 || em == 1) B->mode = em;
+  }
+  bool ok = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) == hipSuccess;
+  for (int c = 0; c < count && ok; ++c)
+    ok = hipStreamCreateWithFlags(&B->br[c], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&B->join[c], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    free_batch(B);
+    return fail(TW_EHIP, "stream or event creation failed");
+  }
+  *out = reinterpret_cast<tw_batch>(B);
+  return TW_OK;
+}
+
+int tw_batch_plan(tw_batch batch, int32_t index, tw_plan* out) {
+  if (!batch || !out) return fail(TW_EINVAL, "NULL batch or output pointer");
+  Batch& B = *reinterpret_cast<Batch*>(batch);
+  if (index < 0 || index >= B.count) return fail(TW_EINVAL, "class index %d out of range", index);
+  *out = reinterpret_cast<tw_plan>(B.plans[index]);
+  return TW_OK;
+}
+
+int tw_batch_destroy(tw_batch batch) {
+  if (!batch) return TW_OK;
+  (void)hipDeviceSynchronize();
+  free_batch(reinterpret_cast<Batch*>(batch));
+  return TW_OK;
+}
+
+int tw_batch_autotune(tw_batch batch, int32_t* variant_out, int32_t* mode_out, void* stream) {
+  if (!batch) return fail(TW_EINVAL, "NULL batch");
+  Batch& B = *reinterpret_cast<Batch*>(batch);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (B.tuned) {
+    if (variant_out) *variant_out = B.variant;
+    if (mode_out) *mode_out = B.mode;
+    return TW_OK;
+  }
+  // scratch: up to 8 pairs of every class
+  void* tmp[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t npt[kMaxClasses];
+  PassArgs base[kMaxClasses];
+  int rc = TW_OK;
+  for (int c = 0; c < B.count && rc == TW_OK; ++c) {
+    Plan& P = *B.plans[c];
+    npt[c] = std::min<int64_t>(P.npairs, 8);
+    const size_t bytes = (size_t)(2 * npt[c]) * P.ncell * P.elem;
+    if (hipMalloc(&tmp[c], bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = fail(TW_ENOMEM, "autotune scratch allocation failed");
+      break;
+    }
+    if (hipMemsetAsync(tmp[c], 0, bytes, s) != hipSuccess || hipMemsetAsync(P.z, 0, npt[c] * P.ncell * P.elem, s) != hipSuccess)
+      rc = fail(TW_EHIP, "scratch clear failed");
+    for (int d = 0; d < P.dim && rc == TW_OK; ++d)
+      if (launch_phase_table(P, d, 1e-4, phase_slot_of(P, d, 1), s) != hipSuccess) rc = fail(TW_EHIP, "tables");
+    Plan Q = P;
+    Q.p.n_real = 2 * npt[c];
+    base[c] = base_args(Q, tmp[c], nullptr, 2 * npt[c]);
+    base[c].n_real = 2 * npt[c];
+    base[c].kick = 1e-4;
+  }
+  double us[2] = {0.0, 0.0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == TW_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(TW_EHIP, "event creation failed");
+  const int modes[5] = {PASS_DRIFT_RHO, PASS_ZPOISSON, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
+  const int keep = B.variant;
+  for (int v = 0; v < 2 && rc == TW_OK; ++v) {
+    B.variant = v;
+    for (int rep = 0; rep < 4 && rc == TW_OK; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) rc = fail(TW_EHIP, "event record failed");
+      for (int d = 1; d < B.dim && rc == TW_OK; ++d)
+        for (int m = 0; m < 5 && rc == TW_OK; ++m) {
+          hipError_t e = grouped(B, base, modes[m], d, 1, s, npt);
+          if (e != hipSuccess) rc = fail(TW_EHIP, "autotune pass: %s", hipGetErrorString(e));
+        }
+      float ms = 0.f;
+      if (rc == TW_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(TW_EHIP, "event timing failed");
+      if (rep > 0) us[v] += 1e3 * ms / 3.0;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  for (int c = 0; c < B.count; ++c)
+    if (tmp[c]) (void)hipFree(tmp[c]);
+  if (rc != TW_OK) {
+    B.variant = keep;
+    return rc;
+  }
+  B.variant = us[1] < us[0] ? 1 : 0;
+  tune_cache_store(batch_key(B), B.variant, us);
+  // per-class organisation for the branch mode, then both modes timed on
+  // full-size scratch ensembles (2 steps each after one warm-up)
+  for (int c = 0; c < B.count; ++c) {
+    const int rc2 = tw_plan_autotune(reinterpret_cast<tw_plan>(B.plans[c]), nullptr, stream);
+    if (rc2 != TW_OK) return rc2;
+  }
+  {
+    void* full[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+    int rc3 = TW_OK;
+    for (int c = 0; c < B.count && rc3 == TW_OK; ++c) {
+      const Plan& P = *B.plans[c];
+      const size_t bytes = (size_t)P.p.n_real * P.ncell * P.elem;
+      if (hipMalloc(&full[c], bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        rc3 = fail(TW_ENOMEM, "autotune scratch allocation failed");
+      } else if (hipMemsetAsync(full[c], 0, bytes, s) != hipSuccess) {
+        rc3 = fail(TW_EHIP, "scratch clear failed");
+      }
+    }
+    double mus[2] = {0.0, 0.0};
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+    if (rc3 == TW_OK && (hipEventCreate(&f0) != hipSuccess || hipEventCreate(&f1) != hipSuccess))
+      rc3 = fail(TW_EHIP, "event creation failed");
+    for (int m = 0; m < 2 && rc3 == TW_OK; ++m) {
+      B.mode = m;
+      for (int rep = 0; rep < 2 && rc3 == TW_OK; ++rep) {
+        if (hipEventRecord(f0, s) != hipSuccess) rc3 = fail(TW_EHIP, "event record failed");
+        if (rc3 == TW_OK) rc3 = enqueue_batch_mode(B, full, nullptr, 2, 1e-4, s);
+        float ms = 0.f;
+        if (rc3 == TW_OK && (hipEventRecord(f1, s) != hipSuccess || hipEventSynchronize(f1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, f0, f1) != hipSuccess))
+          rc3 = fail(TW_EHIP, "event timing failed");
+        if (rep > 0) mus[m] = 1e3 * ms;
+      }
+    }
+    if (f0) (void)hipEventDestroy(f0);
+    if (f1) (void)hipEventDestroy(f1);
+    (void)hipStreamSynchronize(s);
+    for (int c = 0; c < B.count; ++c)
+      if (full[c]) (void)hipFree(full[c]);
+    if (rc3 != TW_OK) return rc3;
+    B.mode = mus[1] < mus[0] ? 1 : 0;
+    tune_cache_store(batch_key(B) + "|mode", B.mode, mus);
+  }
+  B.tuned = 1;
+  if (B.exec) {  // a captured graph used the previous choice
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(B.exec);
+    (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+    B.key_nsteps = -1;
+  }
+  if (variant_out) *variant_out = B.variant;
+  if (mode_out) *mode_out = B.mode;
+  return TW_OK;
+}
+
+int tw_batch_step(tw_batch batch, void* const* psi, void* const* psi_classical, int64_t nsteps, double dt,
+                  void* stream) {
+  if (!batch) return fail(TW_EINVAL, "NULL batch");
+  Batch& B = *reinterpret_cast<Batch*>(batch);
+  if (!psi) return fail(TW_EINVAL, "psi array is NULL");
+  for (int c = 0; c < B.count; ++c) {
+    if (int rc = check_ptr(*B.plans[c], psi[c], "psi[c]", false)) return rc;
+    if (psi_classical)
+      if (int rc = check_ptr(*B.plans[c], psi_classical[c], "psi_classical[c]", true)) return rc;
+  }
+  if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
+  if (nsteps == 0) return TW_OK;
+  bool same = B.exec && B.key_nsteps == nsteps && B.key_dt == dt;
+  for (int c = 0; c < B.count && same; ++c)
+    same = B.key_psi[c] == psi[c] && B.key_cl[c] == (psi_classical ? psi_classical[c] : nullptr);
+  if (!same) {
+    if (B.exec) TW_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));  // old graph may be in flight
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+    B.key_nsteps = -1;
+    TW_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue_batch_mode(B, psi, psi_classical, nsteps, dt, B.cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(B.cap, &g);
+    if (rc != TW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(TW_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+    B.graph = g;
+    TW_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    B.key_nsteps = nsteps;
+    B.key_dt = dt;
+    for (int c = 0; c < B.count; ++c) {
+      B.key_psi[c] = psi[c];
+      B.key_cl[c] = psi_classical ? psi_classical[c] : nullptr;
+    }
+  }
+  TW_HIP(hipGraphLaunch(B.exec, reinterpret_cast<hipStream_t>(stream)));
+  return TW_OK;
 }
 
 }  // extern "C"

@@ -102,6 +102,17 @@ hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t 
 hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
                           const double* energy_dev, hipStream_t s);
 
+// Grouped launch over the size classes of a batch (kernels_batch.hip).
+constexpr int kMaxClasses = 4;
+struct GroupArgs {
+  PassArgs a[kMaxClasses];
+  uint32_t groups[kMaxClasses];     // x-blocks per pair of class c
+  uint32_t start[kMaxClasses + 1];  // first block of class c (filled by the launcher)
+  int32_t nclass;
+};
+hipError_t launch_grouped(bool fp32, int mode, GroupArgs& g, int variant, hipStream_t s);
+bool batch_length_supported(int n);
+
 // Autotuner cache (tune.hip).
 std::string tune_key(const Plan& P);
 int tune_cache_lookup(const std::string& key);

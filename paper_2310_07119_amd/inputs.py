@@ -107,6 +107,9 @@ WORKLOADS = {
                          nsteps=5000, hbar_m=1.0, G=1.0, m_tot=1.0),
     "3d_n128_grf": dict(n=(128, 128, 128), box=(1.0, 1.0, 1.0), n_real=64,
                         n_tot=1e3 * 128 ** 3, dt=1e-4, nsteps=2000, hbar_m=1.0, G=1.0, m_tot=1.0),
+    # three size classes advanced together (FP32 split): 64 realizations each
+    "3d_batched_soliton": dict(classes=((64, 64, 64), (96, 96, 96), (128, 128, 128)), box=(1.0, 1.0, 1.0),
+                               n_real=64, occupation=1e3, dt=1e-4, nsteps=1000, hbar_m=1.0, G=1.0, m_tot=1.0),
 }
 
 
@@ -121,4 +124,6 @@ def initial_field(name, n=None):
         return gaussian_pair_2d(n, box, hbar_m=w["hbar_m"])
     if name == "3d_n128_grf":
         return lognormal_field(n, box, kcut=min(32, min(n) // 2), seed=0)
+    if name == "3d_batched_soliton":
+        return soliton_3d(n, box, core=0.1)
     raise KeyError(name)

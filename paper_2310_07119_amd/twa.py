@@ -24,7 +24,8 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
 
 # Exported entry points and their argument types (mirrors include/tw.h).
 EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_moments",
-           "tw_plan_autotune", "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
+           "tw_plan_autotune", "tw_batch_create", "tw_batch_plan", "tw_batch_autotune", "tw_batch_step",
+           "tw_batch_destroy", "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
 NUM_KERNEL_KINDS = 16
 
 
@@ -60,6 +61,11 @@ def load_library(path=LIB_PATH):
     lib.tw_step.argtypes = [vp, vp, vp, i64, dbl, vp]
     lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
     lib.tw_plan_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.tw_batch_create.argtypes = [ctypes.POINTER(TwProblem), ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.tw_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.tw_batch_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), vp]
+    lib.tw_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, dbl, vp]
+    lib.tw_batch_destroy.argtypes = [vp]
     lib.tw_plan_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.tw_plan_get_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -130,25 +136,39 @@ class Problem:
         return torch.complex128 if self.precision == "fp64" else torch.complex64
 
 
+def _problem_struct(problem):
+    pr = TwProblem()
+    pr.dim = problem.dim
+    for d in range(3):
+        pr.n[d] = problem.n[d] if d < problem.dim else 1
+        pr.box[d] = problem.box[d] if d < problem.dim else 1.0
+    pr.hbar_m, pr.G, pr.m_tot, pr.n_tot = problem.hbar_m, problem.G, problem.m_tot, problem.n_tot
+    pr.n_real = problem.n_real
+    pr.precision = TW_FP64 if problem.precision == "fp64" else TW_FP32_SPLIT
+    pr.reserved = 0
+    return pr
+
+
 class Plan:
     """Owns a tw_plan (tables + device workspace) for one Problem on the current device."""
 
-    def __init__(self, problem: Problem):
+    def __init__(self, problem: Problem, _borrowed=None):
         lib = load_library()
         self.problem = problem
-        pr = TwProblem()
-        pr.dim = problem.dim
-        for d in range(3):
-            pr.n[d] = problem.n[d] if d < problem.dim else 1
-            pr.box[d] = problem.box[d] if d < problem.dim else 1.0
-        pr.hbar_m, pr.G, pr.m_tot, pr.n_tot = problem.hbar_m, problem.G, problem.m_tot, problem.n_tot
-        pr.n_real = problem.n_real
-        pr.precision = TW_FP64 if problem.precision == "fp64" else TW_FP32_SPLIT
-        pr.reserved = 0
+        self._lib = lib
+        if _borrowed is not None:      # a batch's class plan: owned by the batch
+            self._h = None
+            self._borrowed = _borrowed
+            return
+        self._borrowed = None
+        pr = _problem_struct(problem)
         h = ctypes.c_void_p()
         _check(lib.tw_plan_create(ctypes.byref(pr), ctypes.byref(h)), "tw_plan_create")
         self._h = h
-        self._lib = lib
+
+    @property
+    def handle(self):
+        return self._borrowed if self._borrowed is not None else self._h
 
     def close(self):
         if getattr(self, "_h", None):
@@ -171,7 +191,7 @@ class Plan:
         assert psi_cl.dtype == torch.complex128 and psi_cl.is_cuda and psi_cl.is_contiguous()
         out = self.empty_ensemble(psi_cl.device) if out is None else out
         assert out.dtype == self.problem.cdtype and out.is_contiguous()
-        _check(self._lib.tw_sample(self._h, _ptr(psi_cl), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+        _check(self._lib.tw_sample(self.handle, _ptr(psi_cl), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
                                    int(real_offset), _ptr(out), _stream()), "tw_sample")
         return out
 
@@ -180,26 +200,26 @@ class Plan:
         assert psi.dtype == self.problem.cdtype and psi.is_contiguous()
         if psi_classical is not None:
             assert psi_classical.dtype == self.problem.cdtype and psi_classical.is_contiguous()
-        _check(self._lib.tw_step(self._h, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
+        _check(self._lib.tw_step(self.handle, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
                "tw_step")
         return psi
 
     def autotune(self):
         """Measure both strided-pass organisations and keep the faster (tw_plan_autotune)."""
         v = ctypes.c_int32(-1)
-        _check(self._lib.tw_plan_autotune(self._h, ctypes.byref(v), _stream()), "tw_plan_autotune")
+        _check(self._lib.tw_plan_autotune(self.handle, ctypes.byref(v), _stream()), "tw_plan_autotune")
         return int(v.value)
 
     def set_profiling(self, enable=True):
         """Bracket every kernel launch with HIP events on its stream (tw_plan_set_profiling)."""
-        _check(self._lib.tw_plan_set_profiling(self._h, 1 if enable else 0), "tw_plan_set_profiling")
+        _check(self._lib.tw_plan_set_profiling(self.handle, 1 if enable else 0), "tw_plan_set_profiling")
 
     def profile(self):
         """{kernel kind: (launches, total device ms)} since the last call (tw_plan_get_profile)."""
         n = NUM_KERNEL_KINDS
         launches = (ctypes.c_int64 * n)()
         ms = (ctypes.c_double * n)()
-        _check(self._lib.tw_plan_get_profile(self._h, n, launches, ms), "tw_plan_get_profile")
+        _check(self._lib.tw_plan_get_profile(self.handle, n, launches, ms), "tw_plan_get_profile")
         out = {}
         for k in range(n):
             if launches[k]:
@@ -224,10 +244,60 @@ class Plan:
         for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "norm", "energy"):
             setattr(mo, k, out[k].data_ptr() if k in out else None)
         mo.scalars = scal.data_ptr()
-        _check(self._lib.tw_moments(self._h, _ptr(psi), _ptr(psi_classical), ctypes.byref(mo), _stream()),
+        _check(self._lib.tw_moments(self.handle, _ptr(psi), _ptr(psi_classical), ctypes.byref(mo), _stream()),
                "tw_moments")
         vals = scal.cpu().tolist()
         for name, v in zip(SCALAR_NAMES, vals):
             out[name] = v
         out["nonfinite"] = int(out["nonfinite"])
         return out
+
+
+class Batch:
+    """Owns a tw_batch: several size classes advanced by grouped launches from one HIP graph."""
+
+    def __init__(self, problems):
+        lib = load_library()
+        self._lib = lib
+        self.problems = list(problems)
+        arr = (TwProblem * len(self.problems))(*[_problem_struct(p) for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(lib.tw_batch_create(arr, len(self.problems), ctypes.byref(h)), "tw_batch_create")
+        self._h = h
+        self.plans = []
+        for i, p in enumerate(self.problems):
+            ph = ctypes.c_void_p()
+            _check(lib.tw_batch_plan(h, i, ctypes.byref(ph)), "tw_batch_plan")
+            self.plans.append(Plan(p, _borrowed=ph))
+
+    def autotune(self):
+        """Tune the batch (tw_batch_autotune); returns (strided-pass variant, batching mode)."""
+        v = ctypes.c_int32(-1)
+        m = ctypes.c_int32(-1)
+        _check(self._lib.tw_batch_autotune(self._h, ctypes.byref(v), ctypes.byref(m), _stream()), "tw_batch_autotune")
+        return int(v.value), int(m.value)
+
+    def step(self, psis, nsteps, dt, classical=None):
+        n = len(self.problems)
+        assert len(psis) == n
+        for p, x in zip(self.problems, psis):
+            assert x.dtype == p.cdtype and x.is_contiguous()
+        ptrs = (ctypes.c_void_p * n)(*[x.data_ptr() for x in psis])
+        cls = None
+        if classical is not None:
+            cls = (ctypes.c_void_p * n)(*[(x.data_ptr() if x is not None else None) for x in classical])
+        _check(self._lib.tw_batch_step(self._h, ptrs, cls, int(nsteps), float(dt), _stream()), "tw_batch_step")
+        return psis
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for p in self.plans:
+                p._borrowed = None
+            self._lib.tw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
