@@ -195,6 +195,62 @@ int tw_plan_get_profile(tw_plan plan, int32_t n_kinds, int64_t* launches, double
 /* Static name of kernel kind k ("" outside the range). */
 const char* tw_kernel_kind_name(int32_t kind);
 
+/* ------------------------------------------------------- learned surrogate
+ * A Fourier neural operator (Li et al., 2020; not part of the paper) that maps
+ * fields derived from the classical run to the ensemble moments the method
+ * produces. Its dense contractions (pointwise layers, truncated DFTs, weight
+ * gradients) run on BF16 matrix cores with FP32 accumulation; mode mixing,
+ * GELU, biases and reductions run in FP32/FP64.
+ *
+ * Layout: inputs x [B][H][W][c_in], outputs y [B][H][W][c_out], FP32, channel
+ * last. Parameters are one flat FP32 buffer, in order: lift_w [c_in][width],
+ * lift_b [width]; for each layer l: R_re, R_im [2 modes_y][modes_x][width][width]
+ * (modes ky in {0..modes_y-1, H-modes_y..H-1}, kx in {0..modes_x-1}),
+ * W [width][width], b [width]; q1_w [width][proj], q1_b [proj];
+ * q2_w [proj][c_out], q2_b [c_out]. Gradients use the same layout. */
+typedef struct {
+  int32_t H, W;         /* grid */
+  int32_t c_in;         /* input channels */
+  int32_t width;        /* hidden channels */
+  int32_t modes_x;      /* kept kx = 0..modes_x-1 (modes_x <= W/2) */
+  int32_t modes_y;      /* kept ky: modes_y lowest non-negative and negative (2 modes_y <= H) */
+  int32_t layers;       /* Fourier layers, 1..8 */
+  int32_t proj;         /* hidden width of the projection */
+  int32_t c_out;        /* output channels */
+} tw_fno_config;
+typedef struct tw_fno_s* tw_fno;
+
+/* Number of FP32 parameters of the configuration. */
+int64_t tw_fno_param_count(const tw_fno_config* config);
+
+/* Allocate the tables and the activation workspace for up to max_batch fields
+ * (max_batch * H <= 65535). Synchronous. */
+int tw_fno_create(const tw_fno_config* config, int32_t max_batch, tw_fno* out);
+int tw_fno_destroy(tw_fno fno);
+
+/* Deterministic initialisation from `seed` (counter hash): weights uniform in
+ * +-1/sqrt(fan_in), spectral weights uniform in (0, 1/width^2), biases 0. */
+int tw_fno_init_params(tw_fno fno, uint64_t seed, float* params, void* stream);
+
+/* y = network(x) for `batch` fields; keeps the activations in the workspace
+ * for a following tw_fno_backward with the same params and x. */
+int tw_fno_forward(tw_fno fno, const float* params, const float* x, int32_t batch, float* y, void* stream);
+
+/* grads (overwritten) = d(sum dy * y)/d(params) for the last tw_fno_forward. */
+int tw_fno_backward(tw_fno fno, const float* params, const float* x, int32_t batch, const float* dy, float* grads,
+                    void* stream);
+
+/* loss[0] = mean((y - t)^2) over n values (FP64 sum), dy = 2 (y - t) / n (dy and
+ * loss may be NULL). Device pointers. */
+int tw_fno_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream);
+
+/* One bias-corrected Adam step (Kingma and Ba) over n parameters; step >= 1. */
+int tw_fno_adam(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                float eps, int64_t step, void* stream);
+
+/* Message of the last tw_fno_* failure on the calling thread. */
+const char* tw_fno_last_error(void);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* tw_last_error(void);
 

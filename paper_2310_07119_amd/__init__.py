@@ -4,4 +4,4 @@ The compute path is the HIP library ``libtw.so`` (C ABI in include/tw.h);
 ``twa.Plan`` is a thin ctypes binding that marshals torch device tensors and
 the current HIP stream into it.
 """
-from .twa import Batch, Plan, Problem, load_library  # noqa: F401
+from .twa import Batch, Fno, Plan, Problem, load_library  # noqa: F401

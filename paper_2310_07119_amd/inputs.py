@@ -81,6 +81,30 @@ def gaussian_pair_2d(n=(512, 512), box=(1.0, 1.0), width=0.05, sep=0.3, vel=5.0,
     return normalise(out, n, box)
 
 
+def random_gaussian_pair_2d(n, box, rng, hbar_m=1.0):
+    """Random soliton pair for surrogate training: widths in [0.03, 0.07] L,
+    separation in [0.15, 0.4] L along a random direction, speeds in [0, 5]
+    towards each other, random relative phase. `rng` is a numpy Generator."""
+    X, Y = _grid_coords(n, box)
+    out = np.zeros(tuple(reversed(n)), dtype=np.complex128)
+    ang = rng.uniform(0, 2 * np.pi)
+    ex, ey = np.cos(ang), np.sin(ang)
+    sep = rng.uniform(0.15, 0.4)
+    cx0, cy0 = rng.uniform(0.3, 0.7, size=2)
+    for sgn in (+1.0, -1.0):
+        w = rng.uniform(0.03, 0.07) * box[0]
+        v = rng.uniform(0.0, 5.0)
+        ph = rng.uniform(0, 2 * np.pi) if sgn < 0 else 0.0
+        amp = rng.uniform(0.5, 1.5)
+        cx = (cx0 + sgn * 0.5 * sep * ex) * box[0]
+        cy = (cy0 + sgn * 0.5 * sep * ey) * box[1]
+        dx = _min_image(X, cx, box[0])
+        dy = _min_image(Y, cy, box[1])
+        env = amp * np.exp(-(dx ** 2 + dy ** 2) / (4.0 * w * w))
+        out = out + env * np.exp(1j * (-sgn * v * (ex * dx + ey * dy) / hbar_m + ph))
+    return normalise(out, n, box)
+
+
 def soliton_3d(n=(64, 64, 64), box=(1.0, 1.0, 1.0), core=0.1):
     """Ground-state-like core profile rho ~ [1 + 0.091 (r/r_c)^2]^-8, r_c = core*L."""
     X, Y, Z = _grid_coords(n, box)

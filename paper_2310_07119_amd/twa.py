@@ -25,7 +25,9 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
 # Exported entry points and their argument types (mirrors include/tw.h).
 EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_moments",
            "tw_plan_autotune", "tw_batch_create", "tw_batch_plan", "tw_batch_autotune", "tw_batch_step",
-           "tw_batch_destroy", "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
+           "tw_batch_destroy", "tw_fno_param_count", "tw_fno_create", "tw_fno_destroy", "tw_fno_init_params",
+           "tw_fno_forward", "tw_fno_backward", "tw_fno_mse", "tw_fno_adam", "tw_fno_last_error",
+           "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
 NUM_KERNEL_KINDS = 16
 
 
@@ -40,6 +42,11 @@ class TwMomentsOut(ctypes.Structure):
     _fields_ = [("mean_psi", ctypes.c_void_p), ("mean_abs2", ctypes.c_void_p), ("mean_rho", ctypes.c_void_p),
                 ("var_rho", ctypes.c_void_p), ("norm", ctypes.c_void_p), ("energy", ctypes.c_void_p),
                 ("scalars", ctypes.c_void_p)]
+
+
+class TwFnoConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("H", "W", "c_in", "width", "modes_x", "modes_y", "layers", "proj",
+                                                "c_out")]
 
 
 class TwError(RuntimeError):
@@ -66,6 +73,18 @@ def load_library(path=LIB_PATH):
     lib.tw_batch_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), vp]
     lib.tw_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, dbl, vp]
     lib.tw_batch_destroy.argtypes = [vp]
+    pf = ctypes.POINTER(ctypes.c_float)
+    lib.tw_fno_param_count.argtypes = [ctypes.POINTER(TwFnoConfig)]
+    lib.tw_fno_param_count.restype = ctypes.c_int64
+    lib.tw_fno_create.argtypes = [ctypes.POINTER(TwFnoConfig), ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.tw_fno_destroy.argtypes = [vp]
+    lib.tw_fno_init_params.argtypes = [vp, u64, vp, vp]
+    lib.tw_fno_forward.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp]
+    lib.tw_fno_backward.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+    lib.tw_fno_mse.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.tw_fno_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, i64, vp]
+    lib.tw_fno_last_error.restype = ctypes.c_char_p
     lib.tw_plan_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.tw_plan_get_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -73,7 +92,7 @@ def load_library(path=LIB_PATH):
     lib.tw_kernel_kind_name.restype = ctypes.c_char_p
     lib.tw_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("tw_last_error", "tw_kernel_kind_name"):
+        if name not in ("tw_last_error", "tw_kernel_kind_name", "tw_fno_last_error", "tw_fno_param_count"):
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -294,6 +313,75 @@ class Batch:
             for p in self.plans:
                 p._borrowed = None
             self._lib.tw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fno:
+    """Fourier-neural-operator surrogate on the GPU (tw_fno_*): parameters, Adam
+    state and data are torch FP32 device tensors owned here / by the caller."""
+
+    def __init__(self, H=256, W=256, c_in=4, width=32, modes_x=16, modes_y=16, layers=4, proj=128, c_out=2,
+                 max_batch=8, seed=0, device="cuda"):
+        lib = load_library()
+        self._lib = lib
+        self.cfg = TwFnoConfig(H, W, c_in, width, modes_x, modes_y, layers, proj, c_out)
+        self.max_batch = max_batch
+        n = lib.tw_fno_param_count(ctypes.byref(self.cfg))
+        h = ctypes.c_void_p()
+        rc = lib.tw_fno_create(ctypes.byref(self.cfg), max_batch, ctypes.byref(h))
+        if rc != 0:
+            raise TwError(f"tw_fno_create failed: {STATUS.get(rc, rc)}: {lib.tw_fno_last_error().decode()}")
+        self._h = h
+        self.params = torch.empty(n, dtype=torch.float32, device=device)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.step_count = 0
+        self._call(lib.tw_fno_init_params(h, ctypes.c_uint64(seed), _ptr(self.params), _stream()), "init")
+
+    def _call(self, rc, what):
+        if rc != 0:
+            raise TwError(f"tw_fno_{what} failed: {STATUS.get(rc, rc)}: {self._lib.tw_fno_last_error().decode()}")
+
+    def forward(self, x, out=None):
+        b = x.shape[0]
+        assert x.dtype == torch.float32 and x.is_contiguous() and b <= self.max_batch
+        out = torch.empty(x.shape[:3] + (self.cfg.c_out,), dtype=torch.float32, device=x.device) if out is None else out
+        self._call(self._lib.tw_fno_forward(self._h, _ptr(self.params), _ptr(x), b, _ptr(out), _stream()), "forward")
+        return out
+
+    def backward(self, x, dy):
+        self._call(self._lib.tw_fno_backward(self._h, _ptr(self.params), _ptr(x), x.shape[0], _ptr(dy),
+                                             _ptr(self.grads), _stream()), "backward")
+        return self.grads
+
+    def mse(self, y, t, want_grad=True):
+        loss = torch.empty(1, dtype=torch.float32, device=y.device)
+        dy = torch.empty_like(y) if want_grad else None
+        self._call(self._lib.tw_fno_mse(_ptr(y), _ptr(t), y.numel(), _ptr(dy), _ptr(loss), _stream()), "mse")
+        return loss, dy
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        self._call(self._lib.tw_fno_adam(_ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v),
+                                         self.params.numel(), lr, b1, b2, eps, self.step_count, _stream()), "adam")
+
+    def train_step(self, x, t, lr=1e-3):
+        y = self.forward(x)
+        loss, dy = self.mse(y, t)
+        self.backward(x, dy)
+        self.adam(lr)
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tw_fno_destroy(self._h)
             self._h = None
 
     def __del__(self):
