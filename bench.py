@@ -52,6 +52,21 @@ def pass_bytes(kind, elem, ncell, nfield, n_real):
     }.get(kind)
 
 
+def measured_traffic(kind, precision, workload):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter summary
+    (profiles/traffic_<kind>_<workload>_<precision>.json), or None if there is
+    none or the kernel sources changed since the counters were taken."""
+    from paper_2310_07119_amd import traffic
+    fn = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload}_{precision}.json")
+    if not os.path.exists(fn):
+        return None
+    with open(fn) as f:
+        d = json.load(f)
+    if d.get("source_digest") != traffic.source_digest():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
 def run_gpu(wl, precision, steps, warmup, seed=20231007):
     import torch
     from paper_2310_07119_amd import Plan, Problem, inputs
@@ -96,8 +111,9 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     avg_s = total_ms / launches / 1e3
     nbytes = pass_bytes(kind, elem, p.ncell, nfield, p.n_real)
     achieved = nbytes / avg_s / 1e9 if nbytes else None
+    traffic = measured_traffic(kind, precision, wl["name"])
     res["roofline"] = {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                       "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                        "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches}
     res["kernel_ms"] = {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     res["strided_variant"] = variant
@@ -197,6 +213,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -239,6 +256,14 @@ def main():
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)
         log(f"batched: {out['batched']}")
+    if not args.no_surrogate:
+        from paper_2310_07119_amd import surrogate
+        spec = surrogate.DatasetSpec(n=(256, 256), n_real=128, steps=100, dt=1e-4, n_tot=1e6)
+        sres = surrogate.gain_study(spec, n_train=160, n_test=8, epochs=4, batch=8, ref_real=1024, seed=2023)
+        sres["note"] = ("reduced study (160 training ensembles, 4 epochs); the full one is "
+                        "python -m paper_2310_07119_amd.surrogate --full")
+        out["surrogate"] = sres
+        log(f"surrogate: {sres}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
         log(f"cpu oracle: {out['cpu_baseline']}")

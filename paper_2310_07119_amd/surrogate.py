@@ -158,3 +158,33 @@ def gain_study(spec, n_train, n_test, epochs, batch, ref_real, net_kw=None, seed
     }
     net.close()
     return res
+
+
+def main(argv=None):
+    """Surrogate study on the 2D soliton-pair workload:
+    --full : 256^2 fields, 2000 training ensembles of 128 realizations, 100 steps
+             ahead, 4-layer FNO (16 modes, width 32), held-out fields judged
+             against 1024-realization ensembles.
+    default: a reduced study (fewer ensembles and epochs) for quick checks."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--full", action="store_true")
+    ap.add_argument("--train", type=int, default=None)
+    ap.add_argument("--epochs", type=int, default=None)
+    a = ap.parse_args(argv)
+    spec = DatasetSpec(n=(256, 256), n_real=128, steps=100, dt=1e-4, n_tot=1e6, G=1.0, m_tot=1.0)
+    n_train = a.train or (2000 if a.full else 200)
+    epochs = a.epochs or (20 if a.full else 6)
+    res = gain_study(spec, n_train=n_train, n_test=16 if a.full else 8, epochs=epochs, batch=8,
+                     ref_real=1024, seed=2023, log=lambda s: print(s, file=sys.stderr, flush=True))
+    res["workload"] = "2d_n256_soliton_pairs"
+    res["spec"] = dict(grid=list(spec.n), n_real=spec.n_real, steps=spec.steps, dt=spec.dt, n_tot=spec.n_tot)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
