@@ -267,7 +267,8 @@ struct FftStage {
   static constexpr int NB = R / RS;                   // butterflies per thread
   static_assert(R % RS == 0, "every stage radix must divide the points per thread");
 
-  static __device__ __forceinline__ void run(cx<T> (&v)[R], cx<T>* lds, int t, const TwiddleCache<T, N>& tc) {
+  template <class TC>
+  static __device__ __forceinline__ void run(cx<T> (&v)[R], cx<T>* lds, int t, const TC& tc) {
     if constexpr (S > 0) {
       fft_sync<SW>();  // previous stage's LDS writes are visible
 #pragma unroll
@@ -282,7 +283,7 @@ struct FftStage {
       if constexpr (NSB > 1) {
 #pragma unroll
         for (int r = 1; r < RS; ++r) {
-          const cx<T> w = tc.template get<S>(i, r);
+          const cx<T> w = tc.template get<S>(i, r);  // TwiddleCache<T, N, cached>
           v[i + r * NB] = INV ? cmulc(v[i + r * NB], w) : cmul(v[i + r * NB], w);
         }
       }
@@ -307,9 +308,9 @@ struct FftStage {
 // false every thread of the workgroup must make the same calls (the stage
 // barriers are workgroup-wide). `tc` holds this thread's twiddles (loaded from
 // the table twd[e] = W_N^e by TwiddleCache::load).
-template <class T, int N, bool INV, bool SYNC_WAVE>
+template <class T, int N, bool INV, bool SYNC_WAVE, bool CACHED>
 __device__ __forceinline__ void fft_pencil(cx<T> (&v)[N / fft_threads(N)], cx<T>* lds, int t,
-                                           const TwiddleCache<T, N>& tc) {
+                                           const TwiddleCache<T, N, CACHED>& tc) {
   FftStage<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(v, lds, t, tc);
 }
 

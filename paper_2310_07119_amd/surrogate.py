@@ -48,7 +48,7 @@ class DatasetSpec:
                        n_real=n_real, precision=self.precision)
 
 
-def make_dataset(spec, count, seed, n_real=None, device="cuda", noise_offset=0):
+def make_dataset(spec, count, seed, n_real=None, device="cuda", noise_offset=0, log=None):
     """count samples: x [count,H,W,4], t [count,H,W,2] (FP32, device). The
     coherent fields depend on `seed` only; `noise_offset` shifts the sampling
     seeds so two datasets of the same fields have independent noise."""
@@ -72,6 +72,8 @@ def make_dataset(spec, count, seed, n_real=None, device="cuda", noise_offset=0):
         x[i, ..., 3] = (cl.imag / amp).float()
         t[i, ..., 0] = ((mean_rho - rho_cl_t) / spec.rho_bar).float()
         t[i, ..., 1] = (var_rho / spec.rho_bar ** 2 * spec.var_scale).float()
+        if log and (i + 1) % 200 == 0:
+            log(f"generated {i + 1}/{count} ensembles")
     plan.close()
     return x.contiguous(), t.contiguous()
 
@@ -123,7 +125,7 @@ def gain_study(spec, n_train, n_test, epochs, batch, ref_real, net_kw=None, seed
     surrogate, the classical field (no correction, no variance) and the plain
     method with the training ensemble size."""
     t0 = time.perf_counter()
-    xtr, ttr = make_dataset(spec, n_train, seed)
+    xtr, ttr = make_dataset(spec, n_train, seed, log=log)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     xte, tte_ref = make_dataset(spec, n_test, seed + 1, n_real=ref_real)
