@@ -46,19 +46,57 @@ __device__ __forceinline__ cx<T> mul_d(cx<T> a, double f) {
   return {(T)((double)a.re * f), (T)((double)a.im * f)};
 }
 
-// exp(-i * arg) for an FP64 argument. FP64 storage: FP64 sincos.
+// exp(-i * arg) for an FP64 argument. FP64 storage: FP64 sine and cosine.
 // FP32 storage: the argument is reduced modulo 2 pi in FP64 and the reduced
-// angle is evaluated in FP32.
+// angle is evaluated in FP32. Kick phases are small (|dt V / hbar| << 1), so
+// both first try Taylor series of sin and cos on |x| <= pi/4, where the
+// truncated terms are below one unit in the last place (FP64: through x^17 and
+// x^16; FP32: through x^9 and x^10); larger arguments take the library call.
 template <class T>
 __device__ __forceinline__ cx<T> expmi(double arg);
 template <>
 __device__ __forceinline__ cx<double> expmi<double>(double arg) {
+  if (fabs(arg) <= 0.78539816339744830962) {
+    const double x2 = arg * arg;
+    double ps = -1.0 / 355687428096000.0;
+    ps = ps * x2 + 1.0 / 1307674368000.0;
+    ps = ps * x2 - 1.0 / 6227020800.0;
+    ps = ps * x2 + 1.0 / 39916800.0;
+    ps = ps * x2 - 1.0 / 362880.0;
+    ps = ps * x2 + 1.0 / 5040.0;
+    ps = ps * x2 - 1.0 / 120.0;
+    ps = ps * x2 + 1.0 / 6.0;
+    double pc = 1.0 / 20922789888000.0;
+    pc = pc * x2 - 1.0 / 87178291200.0;
+    pc = pc * x2 + 1.0 / 479001600.0;
+    pc = pc * x2 - 1.0 / 3628800.0;
+    pc = pc * x2 + 1.0 / 40320.0;
+    pc = pc * x2 - 1.0 / 720.0;
+    pc = pc * x2 + 1.0 / 24.0;
+    pc = pc * x2 - 0.5;
+    const double s = arg - arg * x2 * ps;
+    const double c = 1.0 + x2 * pc;
+    return {c, -s};
+  }
   double s, c;
   sincos(arg, &s, &c);
   return {c, -s};
 }
 template <>
 __device__ __forceinline__ cx<float> expmi<float>(double arg) {
+  if (fabs(arg) <= 0.78539816339744830962) {
+    const float x = (float)arg, x2 = x * x;
+    float ps = 1.f / 362880.f;
+    ps = ps * x2 - 1.f / 5040.f;
+    ps = ps * x2 + 1.f / 120.f;
+    ps = ps * x2 - 1.f / 6.f;
+    float pc = -1.f / 3628800.f;
+    pc = pc * x2 + 1.f / 40320.f;
+    pc = pc * x2 - 1.f / 720.f;
+    pc = pc * x2 + 1.f / 24.f;
+    pc = pc * x2 - 0.5f;
+    return {1.f + x2 * pc, -(x + x * x2 * ps)};
+  }
   const double two_pi = 6.283185307179586476925286766559;
   double r = arg - two_pi * rint(arg * (1.0 / two_pi));
   float s, c;
