@@ -233,7 +233,6 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
           for (int m = 0; m < R; ++m) {
             v[m] = cmul(v[m], expmi<T>(a.kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
-            __builtin_amdgcn_sched_barrier(0);  // one sincos at a time: bounds live registers
           }
           drift(q, v);
           pencil_put(q, v);

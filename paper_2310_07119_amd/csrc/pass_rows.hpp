@@ -136,7 +136,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       va[m] = cmul(va[m], expmi<T>(a.kick * (double)zv[m].re));
-      __builtin_amdgcn_sched_barrier(0);  // one sincos at a time: bounds live registers
     }
     drift(va);
     store(field_ptr<T>(a, fA), va);
@@ -144,7 +143,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         vb[m] = cmul(vb[m], expmi<T>(a.kick * (double)zv[m].im));
-        __builtin_amdgcn_sched_barrier(0);
       }
       drift(vb);
       store(field_ptr<T>(a, fB), vb);
