@@ -352,13 +352,13 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
   const int64_t bstride = (int64_t)F.max_batch * K2 * mx * C;
   // projection 2
   FNO_HIP(weight_grad(F, s, P, c.proj, c.c_out, F.h, dy, grads + L.q2_w));
-  FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, s));
+  FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, F.parts, F.parts_len, s));
   FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1));
   FNO_HIP(launch_gelu_back(F.dz, F.z1, F.dz, P * c.proj, s));
   // projection 1
   const float* vL = F.v + (int64_t)c.layers * PC;
   FNO_HIP(weight_grad(F, s, P, C, c.proj, vL, F.dz, grads + L.q1_w));
-  FNO_HIP(launch_colsum(F.dz, P, c.proj, grads + L.q1_b, 0, s));
+  FNO_HIP(launch_colsum(F.dz, P, c.proj, grads + L.q1_b, 0, F.parts, F.parts_len, s));
   float* dv = F.t1;
   float* du = F.t2;
   FNO_HIP(gemm(s, P, C, c.proj, 1.f, F.dz, c.proj, 1, params + L.q1_w, 1, c.proj, 0.f, dv, C, 1));
@@ -371,7 +371,7 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
       FNO_HIP(hipMemcpyAsync(du, dv, sizeof(float) * P * C, hipMemcpyDeviceToDevice, s));
     }
     FNO_HIP(weight_grad(F, s, P, C, C, vl, du, grads + L.W[l]));
-    FNO_HIP(launch_colsum(du, P, (int)C, grads + L.b[l], 0, s));
+    FNO_HIP(launch_colsum(du, P, (int)C, grads + L.b[l], 0, F.parts, F.parts_len, s));
     const float* br = F.bsav + (2 * l) * bstride;
     const float* bi = F.bsav + (2 * l + 1) * bstride;
     if (int rc = spectral_bwd(F, s, batch, du, br, bi, params + L.Rre[l], params + L.Rim[l], grads + L.Rre[l],
@@ -380,7 +380,7 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
     FNO_HIP(gemm(s, P, C, C, 1.f, du, C, 1, params + L.W[l], 1, C, 1.f, dv, C, 1));
   }
   FNO_HIP(weight_grad(F, s, P, c.c_in, C, x, dv, grads + L.lift_w));
-  FNO_HIP(launch_colsum(dv, P, (int)C, grads + L.lift_b, 0, s));
+  FNO_HIP(launch_colsum(dv, P, (int)C, grads + L.lift_b, 0, F.parts, F.parts_len, s));
   return TW_OK;
 }
 

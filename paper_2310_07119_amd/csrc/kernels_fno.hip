@@ -10,6 +10,8 @@
 // element strides let the same kernel serve transposed operands, the DFT
 // matrices of the spectral layers and split-K weight gradients.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "fno_internal.hpp"
@@ -146,24 +148,48 @@ hipError_t launch_gelu_back(const float* g, const float* z, float* d, int64_t n,
 
 // out[c] (+)= sum over rows p < P of x[p, c]; one workgroup per column block,
 // FP64 accumulation, fixed order (deterministic).
-__global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ x, int64_t P, int C,
-                                                     float* __restrict__ out, int accumulate) {
+// Column sums of x[P][C] in two deterministic stages: block b sums rows
+// [b*rows, (b+1)*rows) into parts[b][C] (threads laid out channel-fastest so a
+// wavefront reads whole contiguous rows), then sum_parts adds the blocks.
+__global__ void __launch_bounds__(256) colsum_parts_kernel(const float* __restrict__ x, int64_t P, int C, int TC,
+                                                           int64_t rows, float* __restrict__ parts) {
   __shared__ double red[256];
-  const int c = blockIdx.x;
-  double s = 0.0;
-  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += (double)x[p * C + c];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+  const int tid = threadIdx.x;
+  const int RL = 256 / TC;  // row lanes
+  const int c0 = tid % TC, r0 = tid / TC;
+  const int64_t rbeg = (int64_t)blockIdx.x * rows;
+  const int64_t rend = rbeg + rows < P ? rbeg + rows : P;
+  for (int cc = 0; cc < C; cc += TC) {
+    const int c = cc + c0;
+    double s = 0.0;
+    if (r0 < RL && c < C) {
+      for (int64_t r = rbeg + r0; r < rend; r += RL) s += (double)x[r * C + c];
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (r0 == 0 && c < C) {
+      double t = 0.0;
+      for (int q = 0; q < RL; ++q) t += red[q * TC + c0];
+      parts[(int64_t)blockIdx.x * C + c] = (float)t;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = (accumulate ? out[c] : 0.f) + (float)red[0];
 }
 
-hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)C), dim3(256), 0, st, x, P, C, out, accumulate);
-  return hipGetLastError();
+hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, float* parts,
+                         int64_t parts_len, hipStream_t st) {
+  if (P <= 0 || C <= 0) return hipErrorInvalidValue;
+  int TC = 1;
+  while (TC * 2 <= C && TC * 2 <= 64) TC *= 2;
+  int64_t nblk = std::min<int64_t>(512, parts_len / C);
+  nblk = std::min<int64_t>(nblk, (P + 255) / 256);
+  if (nblk < 1) return hipErrorInvalidValue;
+  const int64_t rows = (P + nblk - 1) / nblk;
+  nblk = (P + rows - 1) / rows;
+  hipLaunchKernelGGL(colsum_parts_kernel, dim3((unsigned)nblk), dim3(256), 0, st, x, P, C, TC, rows, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_parts(parts, (int)nblk, C, out, accumulate, st);
 }
 
 // out[i] = sum_j parts[j * n + i]  (split-K reduction), out may accumulate
@@ -276,27 +302,47 @@ hipError_t launch_modemix_bwd(const float* br, const float* bi, const float* dcr
 
 // --------------------------------------------------------------- training
 // loss = (1/n) sum (y - t)^2 (one workgroup, FP64, written to loss[0]); dy = 2 (y - t) / n
-__global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
-                                                  float* __restrict__ dy, float* __restrict__ loss) {
-  __shared__ double red[256];
+// Mean squared error and its gradient. One workgroup of 1024 threads so the
+// loss is reduced in a fixed order without a workspace; four independent
+// elements per thread per iteration keep enough loads in flight.
+__global__ void __launch_bounds__(1024) mse_kernel(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
+                                                   float* __restrict__ dy, float* __restrict__ loss) {
+  __shared__ double red[1024];
+  const int tid = threadIdx.x;
   double s = 0.0;
   const double inv = 1.0 / (double)n;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  constexpr int U = 4;
+  int64_t i = tid;
+  for (; i + (U - 1) * 1024 < n; i += U * 1024) {
+    float yv[U], tv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      yv[u] = y[i + u * 1024];
+      tv[u] = t[i + u * 1024];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double d = (double)yv[u] - (double)tv[u];
+      s += d * d;
+      if (dy) dy[i + u * 1024] = (float)(2.0 * d * inv);
+    }
+  }
+  for (; i < n; i += 1024) {
     const double d = (double)y[i] - (double)t[i];
     s += d * d;
     if (dy) dy[i] = (float)(2.0 * d * inv);
   }
-  red[threadIdx.x] = s;
+  red[tid] = s;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+  for (int off = 512; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && loss) loss[0] = (float)(red[0] * inv);
+  if (tid == 0 && loss) loss[0] = (float)(red[0] * inv);
 }
 
 hipError_t launch_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, st, y, t, n, dy, loss);
+  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, y, t, n, dy, loss);
   return hipGetLastError();
 }
 

@@ -3,10 +3,10 @@
 // that global memory is touched in coalesced tiles and every FFT exchange stays
 // inside one wavefront.
 //
-// A workgroup of 4 wavefronts owns C adjacent pencils (C >= 64 bytes of
-// contiguous elements per row). Each field is moved as a tile: every thread
-// loads K elements row-by-row (consecutive lanes -> consecutive pencils, so a
-// load instruction reads whole 64-byte segments) into a padded LDS tile laid
+// A workgroup of 4 to 8 wavefronts owns C adjacent pencils (C >= 128 bytes of
+// contiguous elements per row, one whole cache line). Each field is moved as a
+// tile: every thread loads K elements row-by-row (consecutive lanes ->
+// consecutive pencils, so a load instruction reads whole lines) into a padded LDS tile laid
 // out pencil-major; after one workgroup barrier each wavefront reads whole
 // pencils out of the tile in the FFT's natural layout, transforms them with
 // wavefront-local exchanges inside that pencil's own slot, and writes them
@@ -23,7 +23,7 @@ struct ColsCfg {
   static constexpr int TPP = fft_threads(N);
   static constexpr int R = N / TPP;
   static constexpr int PPW = 64 / TPP;                       // pencils per wavefront per round
-  static constexpr int COAL = 64 / (int)(2 * sizeof(T));     // pencils per 64 contiguous bytes
+  static constexpr int COAL = 128 / (int)(2 * sizeof(T));    // pencils per 128 contiguous bytes
   // at least 4 wavefronts; up to 8 so that one round covers the tile
   static constexpr int WAVES = (COAL / PPW) > 4 ? ((COAL / PPW) < 8 ? (COAL / PPW) : 8) : 4;
   static constexpr int THREADS = 64 * WAVES;

@@ -1,6 +1,15 @@
-"""HBM traffic of the dominant kernel from rocprofv3 counter runs.
+"""Summaries of rocprofv3 runs: per-kernel durations and the HBM traffic of the
+dominant kernel.
 
-Two steps, each a command of its own:
+  python -m paper_2310_07119_amd.traffic kernels --dir DIR --timed-launches K \
+      --bench-log LOG --command CMD --out FILE.md
+      reads a `rocprofv3 --kernel-trace --stats` output directory and writes a
+      markdown summary: the stats table, and for every pass kernel the average
+      of its last K dispatches (the timed region of a bench run, after the
+      autotuner's and warmup launches) next to the per-launch average the
+      bench measured itself with HIP events (taken from the JSON line in LOG).
+
+The traffic figure takes two counter runs and a calibration:
 
   python -m paper_2310_07119_amd.traffic copy --mib 1024
       a plain device-to-device copy of a known size (run it under
@@ -88,7 +97,87 @@ def summarize(a):
            "source_digest": source_digest(), "commands": a.commands}
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
+    md = os.path.splitext(a.out)[0] + ".md"
+    with open(md, "w") as f:
+        f.write(f"# HBM traffic of {a.kind} (rocprofv3 counters)\n\n"
+                f"Commands (from the repository root, each its own run):\n\n```\n"
+                + a.commands.replace(" ; ", "\n") + "\n```\n\n"
+                f"| quantity | value |\n|---|---:|\n"
+                f"| dispatches averaged (FETCH, WRITE) | {len(fetch)}, {len(write)} |\n"
+                f"| FETCH_SIZE per dispatch, raw KiB | {sum(fetch) / len(fetch):.0f} |\n"
+                f"| WRITE_SIZE per dispatch, raw KiB | {sum(write) / len(write):.0f} |\n"
+                f"| copy calibration ({a.copy_mib} MiB device copy): true bytes / counter bytes, fetch | {f_fac:.4f} |\n"
+                f"| copy calibration, write | {w_fac:.4f} |\n"
+                f"| fetched bytes per launch (scaled) | {fb:.4e} |\n"
+                f"| written bytes per launch (scaled) | {wb:.4e} |\n"
+                f"| total HBM bytes per launch | {fb + wb:.4e} |\n"
+                f"| kernel source digest | `{out['source_digest']}` |\n")
     print(json.dumps(out))
+
+
+def _kind_of(name):
+    """(precision, mode) of a pass kernel from its compiled name, else None."""
+    import re
+    m = re.search(r"(pass|cols)_kernel<(double|float), (\d+), (\d+)", name)
+    if not m:
+        return None
+    return ("fp64" if m.group(2) == "double" else "fp32"), int(m.group(4))
+
+
+MODE_KIND = {0: "pass_drift", 1: "pass_drift_rho", 2: "pass_zfwd", 3: "pass_zpoisson", 4: "pass_zinv",
+             5: "pass_kick_drift", 6: "pass_rho", 7: "pass_kin_sum", 8: "pass_pot_sum"}
+
+
+def kernels(a):
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(a.dir, "**", "*kernel_stats.csv"), recursive=True)[0])))
+    trace = list(csv.DictReader(open(glob.glob(os.path.join(a.dir, "**", "*kernel_trace.csv"), recursive=True)[0])))
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    lines = [f"# rocprofv3 kernel summary: {a.title}", "", "Command (from the repository root):", "",
+             "```", a.command, "```", ""]
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines += ["## --stats table (all dispatches of the run, autotuner and warmup included)", "",
+              "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---:|---:|---:|---:|---:|"]
+    for r in stats[: a.top]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    lines += ["", f"Total kernel time {total / 1e6:.1f} ms.", ""]
+    if a.timed_launches:
+        # last dispatches of every pass kernel name = the timed region of its leg
+        kinds = {}
+        for r in trace:
+            k = _kind_of(r["Kernel_Name"])
+            if k is None:
+                continue
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            kinds.setdefault((k[0], MODE_KIND[k[1]]), []).append((r["Kernel_Name"], dur))
+        bench = {}
+        if a.bench_log:
+            for ln in open(a.bench_log):
+                if ln.startswith("{") and '"metric"' in ln:
+                    d = json.loads(ln)
+                    bench[(d["config"]["precision"], d["roofline"]["kernel"])] = d["roofline"]["avg_launch_ms"] * 1e3
+        lines += [f"## Timed region: pass kernels, last {a.timed_launches} launches of each kind", "",
+                  "The 2D passes alternate the axis they transform every step, so a kind's launches split",
+                  "between its row kernel (`..., true>`) and its strided kernel. Kinds launched fewer times",
+                  "per run than this (moments, energies) include warmup launches.", "",
+                  "| precision | kind | kernel | launches | avg us |", "|---|---|---|---:|---:|"]
+        summary = []
+        for (prec, kind), seq in sorted(kinds.items()):
+            sel = seq[-a.timed_launches:]
+            names = {}
+            for name, d in sel:
+                names.setdefault(name, []).append(d)
+            for name, d in names.items():
+                lines.append(f"| {prec} | {kind} | `{name[:70]}` | {len(d)} | {sum(d) / len(d):.1f} |")
+            summary.append((prec, kind, len(sel), sum(d for _, d in sel) / len(sel)))
+        lines += ["", "| precision | kind | launches | rocprofv3 avg us | bench HIP-event avg us |",
+                  "|---|---|---:|---:|---:|"]
+        for prec, kind, n, avg in summary:
+            b = bench.get((prec, kind))
+            lines.append(f"| {prec} | {kind} | {n} | {avg:.1f} | {f'{b:.1f}' if b else '-'} |")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def copy(a):
@@ -113,9 +202,19 @@ def main():
     s.add_argument("--kind", default="pass_kick_drift")
     s.add_argument("--copy-mib", dest="copy_mib", type=int, default=1024)
     s.add_argument("--commands", default="")
+    k = sub.add_parser("kernels")
+    k.add_argument("--dir", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--command", default="")
+    k.add_argument("--title", default="")
+    k.add_argument("--bench-log", dest="bench_log", default="")
+    k.add_argument("--timed-launches", dest="timed_launches", type=int, default=0)
+    k.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
     if a.cmd == "copy":
         copy(a)
+    elif a.cmd == "kernels":
+        kernels(a)
     else:
         summarize(a)
     return 0
