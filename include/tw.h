@@ -110,6 +110,11 @@ typedef struct {
   double* mean_abs2;  /* [N] <|psi'|^2>_g, Weyl (symmetric) ordering */
   double* mean_rho;   /* [N] <rho>_g = m_tot <|psi'|^2>_g */
   double* var_rho;    /* [N] <(rho - <rho>)^2>_g, plug-in 1/N_s estimator */
+  double* mode_occ;   /* [N] <|a_j|^2> per Fourier mode j (same index layout as the
+                         grid, j in FFT order), a_j = F[alpha]_j / sqrt(N) with
+                         alpha_g = sqrt(n_tot dV) psi'_g (unitary DFT, occupation
+                         units; Sec. "Quantum description"): at sampling time
+                         <|a_j|^2> = |a_cl,j|^2 + 1/2. Averages realizations only */
   double* norm;       /* [n_real] sum_g |psi'|^2 dV per realization */
   double* energy;     /* [n_real] m_tot [ (hbar^2/2) int|grad psi'|^2 + (1/2) int V|psi'|^2 ] */
   double* scalars;    /* [8]: Q_raw, Q_sym, dev_rho_L1, dev_psi_L2, energy_mean,
@@ -122,7 +127,10 @@ typedef struct {
  * (the two deviations need psi_classical, else they are 0); nonfinite_count
  * counts realizations holding a NaN or Inf. All sums are FP64. energy and
  * scalars[4], scalars[7] are computed only when `energy` is non-NULL (they need
- * one spectral transform and one Poisson solve per realization).
+ * one spectral transform and one Poisson solve per realization); mode_occ needs
+ * one full D-dim forward transform per realization. Both use the plan's
+ * spectral scratch and return TW_EUNSUPPORTED for plans with an axis shorter
+ * than 16 points.
  *   psi           : device, [n_real][N] in the plan's precision.
  *   psi_classical : device, [N] in the plan's precision, or NULL. */
 int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,

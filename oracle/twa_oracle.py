@@ -244,7 +244,7 @@ def mode_amplitudes(prob, psi, n_tot):
     return prob.T.fwd(alpha) / np.sqrt(g.ncell)
 
 
-def moments(prob, psi, n_tot, psi_cl=None):
+def moments(prob, psi, n_tot, psi_cl=None, modes=False):
     """Ensemble moments by the plug-in estimator (1/N_s) sum_i (Sec. "Evaluating
     operators"); every Weyl symbol is evaluated per realization and averaged.
 
@@ -259,6 +259,7 @@ def moments(prob, psi, n_tot, psi_cl=None):
       dev_rho_L1 sum_g dV |<rho> - rho_cl| / M_tot          (if psi_cl given)
       dev_psi_L2 sum_g dV |<psi'> - psi'_cl|^2               (if psi_cl given)
       nonfinite  count of realizations holding a non-finite value
+      mode_occ   <|a_j|^2> per Fourier mode, a_j from mode_amplitudes (if modes=True)
     """
     g = prob.grid
     ns = psi.shape[0]
@@ -275,6 +276,9 @@ def moments(prob, psi, n_tot, psi_cl=None):
                Q_raw=q_raw, Q_sym=q_raw - g.ncell / (2.0 * n_tot))
     flat = psi.reshape(ns, -1)
     out["nonfinite"] = int((~np.isfinite(flat)).any(axis=1).sum())
+    if modes:
+        a = mode_amplitudes(prob, psi, n_tot)
+        out["mode_occ"] = (a.real ** 2 + a.imag ** 2).sum(axis=0) / ns
     if psi_cl is not None:
         rho_cl = density(prob, psi_cl)
         out["dev_rho_L1"] = np.abs(mean_rho - rho_cl).sum() * g.dV / prob.m_tot

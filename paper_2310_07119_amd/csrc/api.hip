@@ -48,7 +48,7 @@ struct Prof {
 const char* const kKindNames[KIND_COUNT] = {
     "pass_drift", "pass_drift_rho", "pass_zfwd", "pass_zpoisson", "pass_zinv", "pass_kick_drift",
     "pass_rho", "pass_kin_sum", "pass_pot_sum", "step1d_resident", "sample", "moments",
-    "tables", "field_mean", "energy_finalize", "unused"};
+    "tables", "field_mean", "energy_finalize", "mode_occ"};
 
 // Run launcher f; when profiling, bracket it with events on stream s.
 template <class F>
@@ -461,6 +461,17 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_momen
     TW_HIP(timed(P, KIND_ENERGY, s,
                  [&] { return launch_energy_finalize(P, P.partial, gstride, nfield, ng, energy_dev, s); }));
     TW_HIP(hipMemcpyAsync(out->energy, energy_dev, sizeof(double) * P.p.n_real, hipMemcpyDeviceToDevice, s));
+  }
+  if (out->mode_occ) {
+    if (!P.z) return fail(TW_EUNSUPPORTED, "mode occupations need grid lengths >= 16");
+    // realizations only: slots p hold realization 2p (round 0) or 2p+1 (round 1)
+    PassArgs a = base_args(P, const_cast<void*>(psi), nullptr, P.p.n_real);
+    const int64_t nslots = (P.p.n_real + 1) / 2;
+    for (int k = 0; k < 2; ++k) {
+      TW_HIP(timed(P, KIND_MODES, s, [&] { return launch_gather_round(P, psi, nslots, k, s); }));
+      for (int d = 0; d < P.dim; ++d) TW_HIP(pass(P, a, PASS_ZFWD, d, nullptr, s));
+      TW_HIP(timed(P, KIND_MODES, s, [&] { return launch_mode_occ(P, nslots, k, out->mode_occ, s); }));
+    }
   }
   Plan Q = P;
   // the moment reductions use the region after the energy partials

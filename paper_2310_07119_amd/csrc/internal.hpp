@@ -83,6 +83,7 @@ enum KernelKind : int {
   KIND_TABLES = 12,
   KIND_MEAN = 13,
   KIND_ENERGY = 14,
+  KIND_MODES = 15,
   KIND_COUNT = 16
 };
 
@@ -99,6 +100,8 @@ hipError_t launch_sample(const Plan& P, const void* psi_cl, uint64_t seed, int64
                          void* psi, hipStream_t s);
 hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t gstride, int64_t nfield,
                                   const int ng[4], double* out, hipStream_t s);
+hipError_t launch_gather_round(const Plan& P, const void* psi, int64_t nslots, int k, hipStream_t s);
+hipError_t launch_mode_occ(const Plan& P, int64_t nslots, int accumulate, double* occ, hipStream_t s);
 hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
                           const double* energy_dev, hipStream_t s);
 

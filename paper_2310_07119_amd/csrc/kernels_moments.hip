@@ -215,4 +215,52 @@ hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t 
   return hipGetLastError();
 }
 
+// Mode occupations <|a_j|^2> (Sec. "Quantum description": the field is a sum
+// of mode operators; a_j = F[alpha]_j / sqrt(N) with alpha = sqrt(n_tot dV) psi').
+// Realizations are transformed in two rounds through the pair scratch: round k
+// places realization 2p+k in slot p, the D-dim forward transform runs on every
+// slot, and the squared moduli are added per mode in a fixed order.
+template <class T>
+__global__ void __launch_bounds__(256) gather_round_kernel(const void* __restrict__ psi, int64_t n_real,
+                                                           int64_t ncell, int64_t nslots, int k, void* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots * ncell) return;
+  const int64_t p = i / ncell, g = i - p * ncell;
+  const int64_t r = 2 * p + k;
+  const cx<T>* src = reinterpret_cast<const cx<T>*>(psi);
+  reinterpret_cast<cx<T>*>(z)[i] = r < n_real ? src[r * ncell + g] : cx<T>{(T)0, (T)0};
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) mode_occ_kernel(const void* __restrict__ z, int64_t nslots, int64_t ncell,
+                                                       double scale, int accumulate, double* __restrict__ occ) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ncell) return;
+  const cx<T>* zz = reinterpret_cast<const cx<T>*>(z);
+  double s = 0.0;
+  for (int64_t p = 0; p < nslots; ++p) {
+    const cx<T> v = zz[p * ncell + g];
+    s += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+  }
+  occ[g] = (accumulate ? occ[g] : 0.0) + scale * s;
+}
+
+hipError_t launch_gather_round(const Plan& P, const void* psi, int64_t nslots, int k, hipStream_t s) {
+  const int64_t total = nslots * P.ncell;
+  if (total <= 0) return hipSuccess;
+  dim3 grid((unsigned)((total + 255) / 256));
+  if (P.fp32) hipLaunchKernelGGL(gather_round_kernel<float>, grid, dim3(256), 0, s, psi, P.p.n_real, P.ncell, nslots, k, P.z);
+  else hipLaunchKernelGGL(gather_round_kernel<double>, grid, dim3(256), 0, s, psi, P.p.n_real, P.ncell, nslots, k, P.z);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_occ(const Plan& P, int64_t nslots, int accumulate, double* occ, hipStream_t s) {
+  // |a_j|^2 = n_tot dV |F[psi']_j|^2 / N, averaged over the realizations
+  const double scale = P.p.n_tot * P.dV / ((double)P.ncell * (double)P.p.n_real);
+  dim3 grid((unsigned)((P.ncell + 255) / 256));
+  if (P.fp32) hipLaunchKernelGGL(mode_occ_kernel<float>, grid, dim3(256), 0, s, P.z, nslots, P.ncell, scale, accumulate, occ);
+  else hipLaunchKernelGGL(mode_occ_kernel<double>, grid, dim3(256), 0, s, P.z, nslots, P.ncell, scale, accumulate, occ);
+  return hipGetLastError();
+}
+
 }  // namespace tw

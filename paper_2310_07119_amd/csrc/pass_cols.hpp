@@ -53,7 +53,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
   double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * LS * sizeof(cx<T>));
 
   const int tid = threadIdx.x;
-  const unsigned grp = xcd_pair_remap(bx, nbx);
+  const unsigned grp = xcd_group_remap(bx, nbx);
   const int64_t npencils = a.ncell / N;
   const int64_t stride = a.stride;
   const int64_t pair = a.pair0 + by;

@@ -22,7 +22,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   const int t = ROWS ? tid % TPP : tid / C;
   cx<T>* lds = lds_all + c * fft_lds_stride(N);
   const int64_t npencils = a.ncell / N;
-  const unsigned grp = ROWS ? bx : xcd_pair_remap(bx, nbx);
+  const unsigned grp = ROWS ? bx : xcd_group_remap(bx, nbx);
   const int64_t p = (int64_t)grp * C + c;
   const bool active = p < npencils;
   const int64_t pp = active ? p : 0;

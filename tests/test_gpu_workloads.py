@@ -38,12 +38,13 @@ def test_1d_workload_complete_run_fp64():
     psi = plan.sample(cl, 0)
     clt = cl.clone()
     plan.step(psi, w["nsteps"], w["dt"], clt)
-    m = plan.moments(psi, clt)
+    m = plan.moments(psi, clt, modes=True)
     prob = oracle_problem(p)
     opsi, ocl, om = tw.run(prob, psi_cl, p.n_real, p.n_tot, 0, w["nsteps"], w["dt"])
     tol = TOL["fp64"]
     assert rel(psi.cpu().numpy(), opsi) < tol
     assert rel(clt.cpu().numpy(), ocl) < tol
+    assert rel(m["mode_occ"].cpu().numpy(), tw.moments(prob, opsi, p.n_tot, modes=True)["mode_occ"]) < tol
     for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
         assert rel(m[k].cpu().numpy(), om[k]) < tol, k
     for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2"):
@@ -62,7 +63,7 @@ def test_2d_workload_full_size_sampled(precision):
     psi = plan.sample(cl, seed)
     clt = cl.to(p.cdtype).clone()
     plan.step(psi, nsteps, w["dt"], clt)
-    m = plan.moments(psi, clt)
+    m = plan.moments(psi, clt, modes=True)
     host = psi.cpu().numpy()
     prob = oracle_problem(p)
     tol = TOL[precision]
@@ -72,9 +73,11 @@ def test_2d_workload_full_size_sampled(precision):
             x0 = x0.astype(np.complex64).astype(np.complex128)
         ref = tw.evolve(prob, x0, nsteps, w["dt"])[0]
         assert rel(host[r], ref) < tol, r
-    om = tw.moments(prob, host.astype(np.complex128), p.n_tot, clt.cpu().numpy().astype(np.complex128))
+    om = tw.moments(prob, host.astype(np.complex128), p.n_tot, clt.cpu().numpy().astype(np.complex128), modes=True)
     for k in ("mean_psi", "mean_rho", "var_rho", "norm"):
         assert rel(m[k].cpu().numpy(), om[k]) < 1e-12, k
+    # mode occupations: the GPU transforms in the plan's precision
+    assert rel(m["mode_occ"].cpu().numpy(), om["mode_occ"]) < (1e-12 if precision == "fp64" else 1e-5)
     for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2"):
         assert abs(m[k] - om[k]) < 1e-11 * abs(om[k]), k
     del psi, host

@@ -104,3 +104,43 @@ def test_nonfinite_flag():
     psi = np.ones((4, 8), complex)
     psi[2, 5] = np.nan
     assert tw.moments(prob, psi, 10.0)["nonfinite"] == 1
+
+
+def test_mode_occupation_brute_force_and_parseval():
+    """<|a_j|^2> summed from the DFT's definition on a non-square grid (a swapped
+    axis or a missing 1/sqrt(N) fails it), and Parseval: sum_j <|a_j|^2> equals
+    n_tot dV sum_g <|psi'|^2>_g."""
+    n = (4, 3)
+    grid = tw.Grid(n, (1.0, 0.6))
+    prob = tw.Problem(grid)
+    rng = np.random.default_rng(3)
+    ns, n_tot = 3, 7.0
+    psi = rng.standard_normal((ns, 3, 4)) + 1j * rng.standard_normal((ns, 3, 4))
+    m = tw.moments(prob, psi, n_tot, modes=True)
+    N = 12
+    for jy in range(3):
+        for jx in range(4):
+            acc = 0.0
+            for r in range(ns):
+                s = 0j
+                for y in range(3):
+                    for x in range(4):
+                        s += np.sqrt(n_tot * grid.dV) * psi[r, y, x] * np.exp(-2j * np.pi * (jx * x / 4 + jy * y / 3))
+                acc += abs(s / np.sqrt(N)) ** 2
+            assert abs(m["mode_occ"][jy, jx] - acc / ns) < 1e-12 * max(1.0, acc / ns)
+    assert abs(m["mode_occ"].sum() - n_tot * grid.dV * m["mean_abs2"].sum()) < 1e-12 * m["mode_occ"].sum()
+
+
+def test_mode_occupation_half_quantum_at_t0():
+    """Right after sampling every mode holds its classical occupation plus the
+    Weyl vacuum half quantum: E<|a_j|^2> = |a_cl,j|^2 + 1/2."""
+    n = (16, 8)
+    grid = tw.Grid(n, (1.0, 0.5))
+    prob = tw.Problem(grid)
+    psi_cl = inputs.lognormal_field(n, (1.0, 0.5), seed=4)
+    n_tot, ns = 200.0, 2000
+    psi = tw.sample(grid, psi_cl, ns, n_tot, seed=23)
+    m = tw.moments(prob, psi, n_tot, modes=True)
+    occ_cl = np.abs(tw.mode_amplitudes(prob, psi_cl, n_tot)) ** 2
+    sigma = np.sqrt((2 * occ_cl + 0.5) * 0.5 / ns)
+    assert np.all(np.abs(m["mode_occ"] - occ_cl - 0.5) < 6 * sigma)
