@@ -71,7 +71,10 @@ typedef struct tw_plan_s* tw_plan;
 
 /* Create a plan: validates the problem, builds twiddle and wavenumber tables
  * and allocates the device workspace (about half a field per realization for
- * D >= 2). Synchronous. Uses the current HIP device. */
+ * D >= 2; for D = 2 also a second buffer of n_real + 1 fields, used by the
+ * alternating-storage step schedule, which is skipped if that allocation
+ * fails or TW_TRANSPOSE=0 is set in the environment). Synchronous. Uses the
+ * current HIP device. */
 int tw_plan_create(const tw_problem* problem, tw_plan* out);
 
 /* Release the plan and its workspace. Waits for the device. NULL is a no-op. */
@@ -95,7 +98,10 @@ int tw_sample(tw_plan plan, const void* psi_cl, uint64_t seed, int64_t real_offs
  * space, potential V_k = -4 pi G rho_k / |k|^2 (zero mode removed) from the
  * drifted field's own density, kick exp(-i dt V / hbar), half drift.
  * Adjacent half drifts inside one call are merged; the state on return is
- * exactly that after nsteps complete steps.
+ * exactly that after nsteps complete steps. In D = 2 the fields alternate
+ * between the caller's buffer and the plan's second buffer, transposed, while
+ * the call runs (every pass then reads whole rows); on return they are back in
+ * the caller's buffer in the usual layout.
  *   psi           : device, [n_real][N] fields in the plan's precision, in place.
  *   psi_classical : device, [N] one extra field in the plan's precision that is
  *                   evolved alongside (the noise-free classical run), or NULL.
@@ -139,7 +145,9 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
 /* Autotune the kernel organisation of the passes along strided axes (y, z).
  * Returns at once if the plan's choice is already settled (tuning cache entry,
  * TW_COLS_VARIANT override, or an earlier call). Otherwise it times both
- * available organisations on scratch buffers of this plan's shape
+ * available organisations (on the strided passes a step runs: all of them, or
+ * only the Poisson pass under the D = 2 alternating-storage schedule) on
+ * scratch buffers of this plan's shape
  * (up to 32 pairs of realizations; allocates and frees them), keeps the faster
  * for this plan and records it in the tuning cache ($TW_TUNE_CACHE, else
  * $XDG_CACHE_HOME or $HOME/.cache, file twa_mi355x_tune.json), which later

@@ -1,5 +1,6 @@
 // C ABI: plan management, argument validation and the launch sequences of
 // tw_sample / tw_step / tw_moments (declared in include/tw.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -87,6 +88,7 @@ void free_plan(Plan* P) {
   }
   if (P->phase) (void)hipFree(P->phase);
   if (P->z) (void)hipFree(P->z);
+  if (P->psi_alt) (void)hipFree(P->psi_alt);
   if (P->rho_mean) (void)hipFree(P->rho_mean);
   if (P->partial) (void)hipFree(P->partial);
   if (P->scratch_small) (void)hipFree(P->scratch_small);
@@ -204,6 +206,64 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   const int D = P.dim;
   const int64_t npairs = (nfield + 1) / 2;
   const int64_t chunk = P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P);
+  if (D == 2 && P.transpose2d) {
+    // Alternating storage: the field passes read whole rows along physical axis
+    // `o0` of fields stored o0-contiguous; the kick pass writes its output
+    // transposed into the other buffer of a pair (the caller's fields, the
+    // plan's second field buffer), so the next field pass again reads rows
+    // along the other axis. The density transform stays in the layout of the
+    // fields, and the Poisson pass runs along its strided axis in place. Only
+    // the opening half drift reads fields along a strided axis. Each step moves
+    // the fields once between the buffers; the closing drift puts them back
+    // into the caller's buffer, x-contiguous.
+    char* alt = static_cast<char*>(P.psi_alt);
+    void* buf[2][2] = {{psi, psi_cl}, {alt, alt + P.elem * (size_t)P.p.n_real * (size_t)P.ncell}};
+    for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
+      const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
+      int cur = 0;  // buffer holding the fields
+      // pass along physical axis `ax` over data stored `contig`-contiguous
+      auto go = [&](int mode, int contig, int ax, const void* phase, int t_psi) {
+        PassArgs b = a;
+        const int other = 1 - contig;
+        b.n[0] = P.n[contig];
+        b.n[1] = P.n[other];
+        b.n[2] = 1;
+        b.k2[0] = P.k2[contig];
+        b.k2[1] = P.k2[other];
+        b.axis = ax == contig ? 0 : 1;
+        b.stride = ax == contig ? 1 : P.n[contig];
+        b.twd = P.twd[ax];
+        b.phase = phase;
+        b.pair0 = c0;
+        b.psi = buf[cur][0];
+        b.psi_cl = buf[cur][1];
+        b.t_psi = t_psi;
+        b.psi_t = buf[1 - cur][0];
+        b.psi_cl_t = buf[1 - cur][1];
+        hipError_t e = timed(P, mode, s, [&] { return launch_pass(P, mode, b, s, (int)nc); });
+        if (t_psi) cur = 1 - cur;
+        return e;
+      };
+      int o0 = 0, o1 = 1;  // fields start x-contiguous
+      TW_HIP(go(PASS_DRIFT, 0, 1, phase_slot(1, 0), 0));
+      TW_HIP(go(PASS_DRIFT_RHO, o0, o0, phase_slot(o0, 0), 0));
+      for (int64_t st = 0; st < nsteps; ++st) {
+        const bool last = (st + 1 == nsteps);
+        TW_HIP(go(PASS_ZPOISSON, o0, o1, nullptr, 0));
+        // kick and drift along o0; fields move to the other buffer, o1-contiguous
+        TW_HIP(go(PASS_KICK_DRIFT, o0, o0, phase_slot(o0, last ? 0 : 1), 1));
+        if (!last) {
+          TW_HIP(go(PASS_DRIFT_RHO, o1, o1, phase_slot(o1, 1), 0));
+          std::swap(o0, o1);
+        } else {
+          // closing half drift along o1; transposed back to x-contiguous when o1 is y
+          TW_HIP(go(PASS_DRIFT, o1, o1, phase_slot(o1, 0), o1 != 0 ? 1 : 0));
+        }
+      }
+      if (cur != 0) return fail(TW_EINVAL, "internal: alternating-storage schedule ended in the plan's buffer");
+    }
+    return TW_OK;
+  }
   // Realizations are independent: each chunk of pairs runs every step before
   // the next chunk starts.
   for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
@@ -295,6 +355,8 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   P->npairs = (P->nfield + 1) / 2;
   P->chunk_pairs = 0;  // 0: default_chunk_pairs
   if (const char* env = getenv("TW_CHUNK_PAIRS")) P->chunk_pairs = atoll(env);
+  P->transpose2d = pr->dim == 2 ? 1 : 0;  // 2D: alternating storage, every pass reads rows
+  if (const char* env = getenv("TW_TRANSPOSE")) P->transpose2d = pr->dim == 2 && atoi(env) != 0;
   // strided-pass organisation: tuning cache if it has this shape, else the
   // usual winner (LDS tiles for FP32, interleaved pencils for FP64)
   P->cols_variant = P->fp32 ? 1 : 0;
@@ -353,6 +415,16 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   // need it in 1D too, where n >= 16)
   const bool need_z = pr->dim >= 2 || pass_length_supported(P->n[0]);
   if (need_z) ALLOC(P->z, P->elem * (size_t)P->npairs * (size_t)P->ncell);
+  if (P->transpose2d) {
+    // second field buffer for the alternating-storage schedule; a device too
+    // small for it runs the strided-pass schedule instead
+    const size_t fb = P->elem * (size_t)P->nfield * (size_t)P->ncell;
+    if (hipMalloc(&P->psi_alt, fb) != hipSuccess) {
+      (void)hipGetLastError();
+      P->psi_alt = nullptr;
+      P->transpose2d = 0;
+    }
+  }
   ALLOC(P->rho_mean, sizeof(double) * P->nfield);
   if (pr->dim >= 2) {
     const int v = tune_cache_lookup(tune_key(*P));
@@ -519,7 +591,10 @@ int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream) {
   TW_HIP(hipEventCreate(&e0));
   TW_HIP(hipEventCreate(&e1));
   double us[2] = {0.0, 0.0};
-  const int modes[5] = {PASS_DRIFT_RHO, PASS_ZPOISSON, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
+  // the strided passes a step runs: all five kinds, or with the 2D
+  // alternating-storage schedule only the Poisson pass
+  const int modes[5] = {PASS_ZPOISSON, PASS_DRIFT_RHO, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
+  const int nmodes = (P.dim == 2 && P.transpose2d) ? 1 : 5;
   int rc = TW_OK;
   for (int v = 0; v < 2 && rc == TW_OK; ++v) {
     Q.cols_variant = v;
@@ -527,7 +602,7 @@ int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream) {
     for (int rep = 0; rep < 4 && rc == TW_OK; ++rep) {  // rep 0 warms up
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(TW_EHIP, "event record failed");
       for (int d = 1; d < P.dim && rc == TW_OK; ++d)
-        for (int m = 0; m < 5 && rc == TW_OK; ++m) {
+        for (int m = 0; m < nmodes && rc == TW_OK; ++m) {
           hipError_t e = pass(Q, a, modes[m], d, phase_slot(d, 1), s, 0, npt);
           if (e != hipSuccess) rc = fail(TW_EHIP, "autotune pass: %s", hipGetErrorString(e));
         }
@@ -847,13 +922,14 @@ int tw_batch_autotune(tw_batch batch, int32_t* variant_out, int32_t* mode_out, v
   if (rc == TW_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = fail(TW_EHIP, "event creation failed");
   const int modes[5] = {PASS_DRIFT_RHO, PASS_ZPOISSON, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
+  const int nmodes = 5;  // batches run the in-place schedule
   const int keep = B.variant;
   for (int v = 0; v < 2 && rc == TW_OK; ++v) {
     B.variant = v;
     for (int rep = 0; rep < 4 && rc == TW_OK; ++rep) {
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(TW_EHIP, "event record failed");
       for (int d = 1; d < B.dim && rc == TW_OK; ++d)
-        for (int m = 0; m < 5 && rc == TW_OK; ++m) {
+        for (int m = 0; m < nmodes && rc == TW_OK; ++m) {
           hipError_t e = grouped(B, base, modes[m], d, 1, s, npt);
           if (e != hipSuccess) rc = fail(TW_EHIP, "autotune pass: %s", hipGetErrorString(e));
         }

@@ -30,6 +30,9 @@ struct PassArgs {
   int32_t pot_green;       // PASS_POT_SUM: apply G(k) along the axis before the inverse (D = 1)
   int32_t variant;         // strided passes: 0 = pencil-interleaved, 1 = LDS tiles (see kernels_cols.hip)
   int64_t pair0;           // first pair of this launch (blockIdx.y + pair0)
+  int32_t t_psi;           // row passes: store the fields transposed (element j of pencil p at j * npencils + p)
+  void* psi_t;             // destination of transposed field stores (never the buffer being read)
+  void* psi_cl_t;          // ... its classical-field slot
 };
 
 enum PassMode : int {
@@ -64,11 +67,13 @@ struct Plan {
   int nmax;
   // workspace
   void* z;               // [npairs][N] complex scratch (D >= 2)
+  void* psi_alt;         // [nfield][N] second field buffer (2D alternating storage)
   double* rho_mean;      // [nfield]
   double* partial;       // reductions
   size_t partial_len;    // doubles
   double* scratch_small; // [64] misc device scalars
   int64_t chunk_pairs;   // pairs advanced through all steps together (cache residency)
+  int transpose2d;       // 2D steps use the alternating-storage row schedule
   int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
   int32_t tuned;         // cols_variant came from a measurement or the tuning cache
   // kernel timing (tw_plan_set_profiling)

@@ -55,6 +55,11 @@ __device__ __forceinline__ cx<T>* field_ptr(const PassArgs& a, int64_t f) {
   return f < a.n_real ? reinterpret_cast<cx<T>*>(a.psi) + f * a.ncell : reinterpret_cast<cx<T>*>(a.psi_cl);
 }
 
+template <class T>
+__device__ __forceinline__ cx<T>* field_ptr_t(const PassArgs& a, int64_t f) {
+  return f < a.n_real ? reinterpret_cast<cx<T>*>(a.psi_t) + f * a.ncell : reinterpret_cast<cx<T>*>(a.psi_cl_t);
+}
+
 // Sum of `x` over the workgroup; result valid in thread 0. `red` holds one
 // double per wave.
 __device__ __forceinline__ double block_sum(double x, double* red) {

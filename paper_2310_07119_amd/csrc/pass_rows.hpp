@@ -22,7 +22,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   const int t = ROWS ? tid % TPP : tid / C;
   cx<T>* lds = lds_all + c * fft_lds_stride(N);
   const int64_t npencils = a.ncell / N;
-  const unsigned grp = ROWS ? bx : xcd_group_remap(bx, nbx);
+  const unsigned grp = xcd_group_remap(bx, nbx);
   const int64_t p = (int64_t)grp * C + c;
   const bool active = p < npencils;
   const int64_t pp = active ? p : 0;
@@ -41,6 +41,35 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
       for (int m = 0; m < R; ++m) f[base + (int64_t)(t + TPP * m) * stride] = v[m];
     }
+  };
+  // Transposed store (row passes of the 2D alternating-storage schedule): the
+  // C pencils of the workgroup go through their LDS buffers so that each
+  // store instruction writes C contiguous elements of the transposed field.
+  // The destination is always another buffer than the one this pass reads:
+  // other workgroups may not have loaded their pencils yet.
+  auto store_t = [&](cx<T>* f, const cx<T> (&v)[R]) {
+    __syncthreads();  // every wavefront is done with its transform's LDS traffic
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[lds_pad(t + TPP * m)] = v[m];
+    __syncthreads();
+    const int cc = tid % C, jj = tid / C;
+    const int64_t pc = (int64_t)grp * C + cc;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int j = jj + TPP * m;
+      const cx<T> w = lds_all[cc * fft_lds_stride(N) + lds_pad(j)];
+      if (pc < npencils) f[(int64_t)j * npencils + pc] = w;
+    }
+    __syncthreads();
+  };
+  auto store_psi = [&](int64_t f, const cx<T> (&v)[R]) {
+    if constexpr (ROWS) {
+      if (a.t_psi) {
+        store_t(field_ptr_t<T>(a, f), v);
+        return;
+      }
+    }
+    store(field_ptr<T>(a, f), v);
   };
   auto zero = [&](cx<T> (&v)[R]) {
 #pragma unroll
@@ -80,18 +109,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 
   if constexpr (MODE == PASS_DRIFT) {
     drift(va);
-    store(field_ptr<T>(a, fA), va);
+    store_psi(fA, va);
     if (hasB) {
       drift(vb);
-      store(field_ptr<T>(a, fB), vb);
+      store_psi(fB, vb);
     }
   } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
     if constexpr (MODE == PASS_DRIFT_RHO) {
       drift(va);
-      store(field_ptr<T>(a, fA), va);
+      store_psi(fA, va);
       if (hasB) {
         drift(vb);
-        store(field_ptr<T>(a, fB), vb);
+        store_psi(fB, vb);
       }
     }
     double ra[R], rb[R];
@@ -138,14 +167,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       va[m] = cmul(va[m], expmi<T>(a.kick * (double)zv[m].re));
     }
     drift(va);
-    store(field_ptr<T>(a, fA), va);
+    store_psi(fA, va);
     if (hasB) {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         vb[m] = cmul(vb[m], expmi<T>(a.kick * (double)zv[m].im));
       }
       drift(vb);
-      store(field_ptr<T>(a, fB), vb);
+      store_psi(fB, vb);
     }
   } else if constexpr (MODE == PASS_KIN_SUM) {
     const double* __restrict__ k2a = a.k2[a.axis];

@@ -54,8 +54,8 @@ std::string tune_key(const Plan& P) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s|D%d|%dx%dx%d|%s|pairs%lld", arch.c_str(), P.dim, P.n[0], P.n[1], P.n[2],
-           P.fp32 ? "fp32" : "fp64", (long long)P.npairs);
+  snprintf(buf, sizeof(buf), "%s|D%d|%dx%dx%d|%s|pairs%lld%s", arch.c_str(), P.dim, P.n[0], P.n[1], P.n[2],
+           P.fp32 ? "fp32" : "fp64", (long long)P.npairs, P.transpose2d ? "|alt" : "");
   return buf;
 }
 

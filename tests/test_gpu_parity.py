@@ -106,3 +106,30 @@ def test_nonfinite_realization_is_counted():
     psi[2, 3, 4] = float("nan")
     m = plan.moments(psi, energy=False)
     assert m["nonfinite"] == 1
+
+
+@pytest.mark.parametrize("transpose", ["0", "1"])
+@pytest.mark.parametrize("nsteps", [5, 6])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_2d_schedules_vs_oracle(precision, nsteps, transpose, monkeypatch):
+    """Both 2D step schedules (strided passes in place / alternating storage with
+    transposed stores into a second buffer) on a grid with many workgroups per
+    pass, odd and even step counts (the alternating schedule ends in the
+    caller's buffer either way)."""
+    monkeypatch.setenv("TW_TRANSPOSE", transpose)
+    n, nr, n_tot = (256, 96), 41, 1e5
+    p = Problem(n=n, box=(1.0, 0.375), hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=n_tot, n_real=nr, precision=precision)
+    psi_cl = inputs.lognormal_field(n, p.box, kcut=16, seed=3)
+    seed, dt = 4242, 2e-4
+    print(f"2d schedule transpose={transpose} nsteps={nsteps} {precision}", flush=True)
+    g = gpu_run(p, psi_cl, seed, nsteps, dt)
+    prob = oracle_problem(p)
+    psi0 = g["psi0"].astype(np.complex128)
+    psi = tw.evolve(prob, psi0, nsteps, dt)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64).astype(np.complex128)
+    cl = tw.evolve(prob, cl0, nsteps, dt)
+    tol = TOL[precision]
+    assert rel(g["psi"], psi) < tol
+    assert rel(g["cl"], cl) < tol
+    for r in (0, 17, 40):
+        assert rel(g["psi"][r], psi[r]) < tol, r
