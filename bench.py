@@ -13,6 +13,9 @@ Extra objects in the line:
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the workload
   fp32_split    the FP32-split form on the same workload, with its normwise error
                 against the FP64 run for each per-cell moment
+  adaptive      the same workload with step sizes chosen on the device
+  batched       the three-size 3D soliton ensemble advanced from one HIP graph
+  surrogate     the reduced FNO surrogate study
 """
 import argparse
 import json
@@ -123,6 +126,37 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     return res
 
 
+def run_adaptive(wl, precision, steps, warmup, seed=20231007, courant=0.5):
+    """The same workload advanced by tw_step_adaptive (step sizes chosen on the
+    device from max|V| and the kinetic bound, no host synchronisation), timed
+    like the fixed-step run; reports the step sizes it chose."""
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision=precision)
+    plan = Plan(p)
+    plan.autotune()
+    cl = torch.from_numpy(inputs.initial_field(wl["name"])).cuda()
+    psi = plan.sample(cl, seed)
+    clt = cl.to(p.cdtype).clone()
+    dt_max = 10.0 * wl["dt"]
+    if warmup > 0:
+        plan.step_adaptive(psi, warmup, dt_max, courant, clt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dts = plan.step_adaptive(psi, steps, dt_max, courant, clt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = dts.cpu()
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
+    return {"value": p.n_real * p.ncell * steps / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
+            "courant": courant, "dt_max": dt_max, "dt_min_chosen": float(d.min()), "dt_max_chosen": float(d.max()),
+            "simulated_time": float(d.sum()), "timed": "tw_step_adaptive only (no sampling or moments)"}
+
+
 def run_batched(steps, warmup, seed=7):
     """The three-size 3D soliton ensemble (FP32 split) advanced as one batch:
     every pass is one grouped launch over all classes and the K steps are one
@@ -213,6 +247,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -253,6 +288,10 @@ def main():
             "err_vs_fp64": {k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")},
         }
         log(f"fp32: {r32['value']:.4e}, errors {out['fp32_split']['err_vs_fp64']}")
+    if not args.no_adaptive:
+        out["adaptive"] = run_adaptive(wl, args.precision, args.steps, args.warmup)
+        out["adaptive"]["fixed_step_ms_per_step"] = main_run["ms_per_step"]
+        log(f"adaptive: {out['adaptive']}")
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)
         log(f"batched: {out['batched']}")

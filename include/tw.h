@@ -109,6 +109,27 @@ int tw_sample(tw_plan plan, const void* psi_cl, uint64_t seed, int64_t real_offs
 int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt,
             void* stream);
 
+/* tw_step with step sizes chosen on the device (the time-step rule of Sec.
+ * "Integrating the equations of motion" and its footnote on the kinetic
+ * bound). Every step n has one size dt_n for all fields:
+ *   dt = min(dt_max, courant * dt_K, courant * 2 pi hbar / max|V|),
+ *   dt_K = min over axes of 4 pi / (hbar k_max dk), k_max = pi/dx, dk = 2 pi/L,
+ * with max|V| over every cell of every field (realizations and the classical
+ * field). Steps 0 and 1 use the potential of the fields on entry; step n + 2
+ * uses the potential evaluated inside step n (the kick pass records its
+ * maximum, and the merged half drifts between steps n and n + 1 need dt_{n+1}
+ * before step n's potential exists). No host synchronisation: a small kernel
+ * after each kick pass turns the recorded maximum into the next step size and
+ * drift tables.
+ *   dt_max  : > 0, upper bound on every step (also the step when nothing else binds).
+ *   courant : c_f in (0, 1].
+ *   dt_out  : device, [nsteps] doubles receiving dt_n (the elapsed time is their
+ *             sum), or NULL.
+ * D >= 2 only (TW_EUNSUPPORTED for D = 1, whose fields are advanced by a
+ * resident kernel that never leaves the workgroup). Other arguments as tw_step. */
+int tw_step_adaptive(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt_max,
+                     double courant, double* dt_out, void* stream);
+
 /* Outputs of tw_moments. Every pointer is a caller-owned device array and may
  * be NULL to skip that output. */
 typedef struct {

@@ -211,6 +211,49 @@ def evolve(prob, psi, nsteps, dt):
     return psi
 
 
+# ------------------------------------------------------------ adaptive step
+def kinetic_dt_bound(prob):
+    """Kinetic step bound of the time-step footnote (Sec. "Numerical
+    implementation"): the phase gradient must not alias, dt < 4 pi / (hbar
+    k_max dk), with k_max = pi / dx (the largest wavenumber on the grid; the
+    printed hbar/2/dx is read as garbled) and dk = 2 pi / L; the smallest over
+    the axes."""
+    g = prob.grid
+    out = np.inf
+    for n, L in zip(g.n, g.box):
+        dx = L / n
+        out = min(out, 4.0 * np.pi / (prob.hbar * (np.pi / dx) * (2.0 * np.pi / L)))
+    return out
+
+
+def adaptive_dt(prob, vmax, dt_max, courant):
+    """Step size from the rule of Sec. "Integrating the equations of motion":
+    c_f times the smaller of the potential bound 2 pi hbar / max|V| (the kick
+    phase stays below 2 pi c_f) and the kinetic bound, never above dt_max."""
+    dt = min(dt_max, courant * kinetic_dt_bound(prob))
+    if vmax > 0.0:
+        dt = min(dt, courant * 2.0 * np.pi * prob.hbar / vmax)
+    return dt
+
+
+def evolve_adaptive(prob, psi, nsteps, dt_max, courant):
+    """Leapfrog steps whose sizes follow `adaptive_dt`, one size for all fields
+    (psi holds every field, classical one included, on its leading axis).
+    Steps 0 and 1 take their size from the potential of the initial fields;
+    step n + 2 from the potential evaluated inside step n (the one the kick of
+    step n uses). Returns (psi, step sizes)."""
+    vm0 = float(np.abs(potential(prob, density(prob, psi))).max())
+    dts = [adaptive_dt(prob, vm0, dt_max, courant)] * 2
+    for n in range(int(nsteps)):
+        dt = dts[n]
+        psi = drift(prob, psi, dt / 2.0)
+        V = potential(prob, density(prob, psi))
+        dts.append(adaptive_dt(prob, float(np.abs(V).max()), dt_max, courant))
+        psi = kick(prob, psi, V, dt)
+        psi = drift(prob, psi, dt / 2.0)
+    return psi, np.array(dts[: int(nsteps)])
+
+
 # ------------------------------------------------------------- diagnostics
 def norm(prob, psi):
     """sum_g |psi'_g|^2 dV per realization (1 for a normalised field)."""

@@ -92,6 +92,8 @@ void free_plan(Plan* P) {
   if (P->rho_mean) (void)hipFree(P->rho_mean);
   if (P->partial) (void)hipFree(P->partial);
   if (P->scratch_small) (void)hipFree(P->scratch_small);
+  if (P->adapt) (void)hipFree(P->adapt);
+  if (P->adapt_tab) (void)hipFree(P->adapt_tab);
   if (P->prof) {
     Prof* pr = static_cast<Prof*>(P->prof);
     for (auto& r : pr->recs) {
@@ -177,17 +179,48 @@ int64_t default_chunk_pairs(const Plan& P) { return P.npairs; }
 namespace tw {
 namespace {
 
-// The launch sequence of tw_step on stream s (arguments already validated).
-int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hipStream_t s) {
+// Device-chosen step sizes (tw_step_adaptive).
+struct Adapt {
+  double dt_max, courant, dtk;
+  double* dt_out;
+};
+
+// Kinetic bound on the step (footnote on the time step of Sec. "Numerical
+// implementation"): the phase gradient must not alias, dt < 4 pi /
+// (hbar k_max dk) with k_max = pi/dx and dk = 2 pi/L, per axis.
+double kinetic_dt_bound(const Plan& P) {
+  double b = INFINITY;
+  for (int d = 0; d < P.dim; ++d) {
+    const double L = P.p.box[d], dx = L / P.n[d];
+    b = std::min(b, 4.0 * M_PI / (P.p.hbar_m * (M_PI / dx) * (2.0 * M_PI / L)));
+  }
+  return b;
+}
+
+// The launch sequence of tw_step / tw_step_adaptive on stream s (arguments
+// already validated). With `ad`, the kick factor and the drift tables of every
+// step come from device memory, written by launch_adapt after each kick pass.
+int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hipStream_t s,
+                 const Adapt* ad = nullptr) {
   const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
   const double h = 0.5 * dt;
   // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
   auto phase_slot = [&](int axis, int full) -> void* {
     return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
   };
-  for (int d = 0; d < P.dim; ++d) {
-    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
-    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
+  auto adapt_slot = [&](int set, int axis) -> void* {
+    return reinterpret_cast<char*>(P.adapt_tab) + sizeof(double) * 2 * (size_t)P.nmax * (3 * set + axis);
+  };
+  // drift factors of the opening half drift, and of step st (merged, or the closing half)
+  auto ph_open = [&](int axis) -> const void* { return ad ? adapt_slot(2, axis) : phase_slot(axis, 0); };
+  auto ph_step = [&](int axis, int64_t st, bool last) -> const void* {
+    return ad ? adapt_slot((int)(st % 2), axis) : phase_slot(axis, last ? 0 : 1);
+  };
+  if (!ad) {
+    for (int d = 0; d < P.dim; ++d) {
+      TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
+      TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
+    }
   }
   if (P.fp32)
     TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
@@ -205,7 +238,35 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   a.rho_mean = P.fp32 ? P.rho_mean : nullptr;
   const int D = P.dim;
   const int64_t npairs = (nfield + 1) / 2;
-  const int64_t chunk = P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P);
+  const int64_t chunk = ad ? npairs : (P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P));
+  if (ad) {
+    // max |V| of the initial fields (the potential passes of the energy), then
+    // the sizes of steps 0 and 1 and their drift tables
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_adapt_clear(P, s); }));
+    PassArgs b = a;
+    b.vmax = P.adapt + 5;
+    b.partial = P.partial;
+    TW_HIP(pass(P, b, PASS_RHO, 0, nullptr, s));
+    for (int d = 1; d < D - 1; ++d) TW_HIP(pass(P, b, PASS_ZFWD, d, nullptr, s));
+    TW_HIP(pass(P, b, PASS_ZPOISSON, D - 1, nullptr, s));
+    for (int d = D - 2; d >= 1; --d) TW_HIP(pass(P, b, PASS_ZINV, d, nullptr, s));
+    TW_HIP(pass(P, b, PASS_POT_SUM, 0, nullptr, s));
+    TW_HIP(timed(P, KIND_TABLES, s, [&] {
+      return launch_adapt(P, -1, nsteps == 1, ad->dt_max, ad->courant, ad->dtk, ad->dt_out, s);
+    }));
+  }
+  // kick pass of step st: the kick factor and max |V| slot of the adaptive state
+  auto kick_args = [&](PassArgs& b, int64_t st) {
+    if (!ad) return;
+    b.kick_dev = P.adapt + 6 + st % 2;
+    b.vmax = P.adapt + 3 + st % 3;
+  };
+  auto after_kick = [&](int64_t st) -> hipError_t {
+    if (!ad) return hipSuccess;
+    return timed(P, KIND_TABLES, s, [&] {
+      return launch_adapt(P, st, st + 2 == nsteps, ad->dt_max, ad->courant, ad->dtk, ad->dt_out, s);
+    });
+  };
   if (D == 2 && P.transpose2d) {
     // Alternating storage: the field passes read whole rows along physical axis
     // `o0` of fields stored o0-contiguous; the kick pass writes its output
@@ -222,8 +283,9 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
       const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
       int cur = 0;  // buffer holding the fields
       // pass along physical axis `ax` over data stored `contig`-contiguous
-      auto go = [&](int mode, int contig, int ax, const void* phase, int t_psi) {
+      auto go = [&](int mode, int contig, int ax, const void* phase, int t_psi, int64_t kick_step = -1) {
         PassArgs b = a;
+        if (kick_step >= 0) kick_args(b, kick_step);
         const int other = 1 - contig;
         b.n[0] = P.n[contig];
         b.n[1] = P.n[other];
@@ -245,19 +307,20 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
         return e;
       };
       int o0 = 0, o1 = 1;  // fields start x-contiguous
-      TW_HIP(go(PASS_DRIFT, 0, 1, phase_slot(1, 0), 0));
-      TW_HIP(go(PASS_DRIFT_RHO, o0, o0, phase_slot(o0, 0), 0));
+      TW_HIP(go(PASS_DRIFT, 0, 1, ph_open(1), 0));
+      TW_HIP(go(PASS_DRIFT_RHO, o0, o0, ph_open(o0), 0));
       for (int64_t st = 0; st < nsteps; ++st) {
         const bool last = (st + 1 == nsteps);
         TW_HIP(go(PASS_ZPOISSON, o0, o1, nullptr, 0));
         // kick and drift along o0; fields move to the other buffer, o1-contiguous
-        TW_HIP(go(PASS_KICK_DRIFT, o0, o0, phase_slot(o0, last ? 0 : 1), 1));
+        TW_HIP(go(PASS_KICK_DRIFT, o0, o0, ph_step(o0, st, last), 1, st));
+        TW_HIP(after_kick(st));
         if (!last) {
-          TW_HIP(go(PASS_DRIFT_RHO, o1, o1, phase_slot(o1, 1), 0));
+          TW_HIP(go(PASS_DRIFT_RHO, o1, o1, ph_step(o1, st, false), 0));
           std::swap(o0, o1);
         } else {
           // closing half drift along o1; transposed back to x-contiguous when o1 is y
-          TW_HIP(go(PASS_DRIFT, o1, o1, phase_slot(o1, 0), o1 != 0 ? 1 : 0));
+          TW_HIP(go(PASS_DRIFT, o1, o1, ph_step(o1, st, true), o1 != 0 ? 1 : 0));
         }
       }
       if (cur != 0) return fail(TW_EINVAL, "internal: alternating-storage schedule ended in the plan's buffer");
@@ -271,26 +334,30 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
     auto run = [&](int mode, int axis, const void* phase) { return pass(P, a, mode, axis, phase, s, c0, nc); };
     int o[3] = {0, 1, 2};
     // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
-    for (int i = D - 1; i >= 1; --i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
-    TW_HIP(run(PASS_DRIFT_RHO, o[0], phase_slot(o[0], 0)));
+    for (int i = D - 1; i >= 1; --i) TW_HIP(run(PASS_DRIFT, o[i], ph_open(o[i])));
+    TW_HIP(run(PASS_DRIFT_RHO, o[0], ph_open(o[0])));
     for (int64_t st = 0; st < nsteps; ++st) {
       const bool last = (st + 1 == nsteps);
-      const int full = last ? 0 : 1;
       // rest of the forward transform of rho, Green's function, inverse (all but o[0])
       for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_ZFWD, o[i], nullptr));
       TW_HIP(run(PASS_ZPOISSON, o[D - 1], nullptr));
       for (int i = D - 2; i >= 1; --i) TW_HIP(run(PASS_ZINV, o[i], nullptr));
       // last inverse along o[0] -> V, kick, drift along o[0]
-      TW_HIP(run(PASS_KICK_DRIFT, o[0], phase_slot(o[0], full)));
+      {
+        PassArgs b = a;
+        kick_args(b, st);
+        TW_HIP(pass(P, b, PASS_KICK_DRIFT, o[0], ph_step(o[0], st, last), s, c0, nc));
+      }
+      TW_HIP(after_kick(st));
       if (!last) {
-        for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 1)));
-        TW_HIP(run(PASS_DRIFT_RHO, o[D - 1], phase_slot(o[D - 1], 1)));
+        for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], ph_step(o[i], st, false)));
+        TW_HIP(run(PASS_DRIFT_RHO, o[D - 1], ph_step(o[D - 1], st, false)));
         // reverse the axis order so the density transform just made is the first one
         int r[3] = {0, 0, 0};
         for (int i = 0; i < D; ++i) r[i] = o[D - 1 - i];
         for (int i = 0; i < D; ++i) o[i] = r[i];
       } else {
-        for (int i = 1; i < D; ++i) TW_HIP(run(PASS_DRIFT, o[i], phase_slot(o[i], 0)));
+        for (int i = 1; i < D; ++i) TW_HIP(run(PASS_DRIFT, o[i], ph_step(o[i], st, true)));
       }
     }
   }
@@ -454,6 +521,10 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   P->partial_len = (size_t)(energy_part + mom_part);
   ALLOC(P->partial, sizeof(double) * P->partial_len);
   ALLOC(P->scratch_small, sizeof(double) * 64);
+  if (pr->dim >= 2) {
+    ALLOC(P->adapt, sizeof(double) * 16);
+    ALLOC(P->adapt_tab, sizeof(double) * 2 * 3 * 3 * (size_t)P->nmax);
+  }
 #undef ALLOC
   *out = reinterpret_cast<tw_plan>(P);
   return TW_OK;
@@ -489,6 +560,23 @@ int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, vo
   if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
   if (nsteps == 0) return TW_OK;
   return enqueue_step(P, psi, psi_cl, nsteps, dt, reinterpret_cast<hipStream_t>(stream));
+}
+
+int tw_step_adaptive(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt_max, double courant,
+                     double* dt_out, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (int rc = check_ptr(P, psi, "psi", false)) return rc;
+  if (int rc = check_ptr(P, psi_cl, "psi_classical", true)) return rc;
+  if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
+  if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(TW_EINVAL, "dt_max must be positive and finite");
+  if (!(courant > 0.0) || !(courant <= 1.0)) return fail(TW_EINVAL, "courant must be in (0, 1]");
+  if (P.dim < 2 || !P.z || !P.adapt) return fail(TW_EUNSUPPORTED, "adaptive steps need D >= 2 (all axes >= 16 points)");
+  if (P.chunk_pairs > 0 && P.chunk_pairs < P.npairs)
+    return fail(TW_EUNSUPPORTED, "adaptive steps need the whole ensemble in one chunk (TW_CHUNK_PAIRS)");
+  if (nsteps == 0) return TW_OK;
+  Adapt ad{dt_max, courant, kinetic_dt_bound(P), dt_out};
+  return enqueue_step(P, psi, psi_cl, nsteps, dt_max, reinterpret_cast<hipStream_t>(stream), &ad);
 }
 
 int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_moments_out* out, void* stream) {

@@ -33,6 +33,8 @@ struct PassArgs {
   int32_t t_psi;           // row passes: store the fields transposed (element j of pencil p at j * npencils + p)
   void* psi_t;             // destination of transposed field stores (never the buffer being read)
   void* psi_cl_t;          // ... its classical-field slot
+  const double* kick_dev;  // PASS_KICK_DRIFT: kick factor dt/hbar read from device memory (overrides kick)
+  double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V| (atomic max on the bits)
 };
 
 enum PassMode : int {
@@ -72,6 +74,8 @@ struct Plan {
   double* partial;       // reductions
   size_t partial_len;    // doubles
   double* scratch_small; // [64] misc device scalars
+  double* adapt;         // [16] adaptive-step state: dt ring [3], max|V| slots [3], kick factors [2]
+  void* adapt_tab;       // cx<double>[3][3][nmax]: drift tables of the adaptive schedule
   int64_t chunk_pairs;   // pairs advanced through all steps together (cache residency)
   int transpose2d;       // 2D steps use the alternating-storage row schedule
   int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
@@ -99,6 +103,13 @@ int cols_pencils_per_group(int n, bool fp32);
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* phase_half, const void* phase_full, double kick, hipStream_t s);
 hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hipStream_t s);
+// Adaptive time step: after the kick pass of step `step` (or, with step = -1,
+// after the initial potential), choose the size of step + 2 (steps 0 and 1)
+// from the recorded max |V|, log dt_out[step], and build the drift tables of
+// step + 1 (merged half drifts, or the closing half drift if last_next).
+hipError_t launch_adapt(const Plan& P, int64_t step, int last_next, double dt_max, double courant, double dtk,
+                        double* dt_out, hipStream_t s);
+hipError_t launch_adapt_clear(const Plan& P, hipStream_t s);
 hipError_t launch_field_mean(const Plan& P, const void* psi, const void* psi_cl, int64_t nfield,
                              double* out_mean, hipStream_t s);
 hipError_t launch_sample(const Plan& P, const void* psi_cl, uint64_t seed, int64_t real_offset,

@@ -229,6 +229,105 @@ hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hi
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- adaptive step
+// State (doubles): [0..2] step sizes dt_n at slot n mod 3; [3..5] running
+// max |V| recorded by the kick pass of step n at slot 3 + n mod 3 (slot 5 also
+// holds the initial potential's); [6..7] kick factor dt_n / hbar at 6 + n mod 2.
+// Drift tables: adapt_tab[p][axis] for steps of parity p, adapt_tab[2][axis]
+// for the opening half drift.
+struct AdaptArgs {
+  double* st;
+  cx<double>* tab;
+  const double* k2[3];
+  int n[3];
+  int dim;
+  int nmax;
+  double hbar, dt_max, courant, dtk;
+  int64_t step;
+  int last_next;
+  double* dt_out;
+};
+
+// Time-step rule: dt = min(dt_max, c_f * dt_kinetic, c_f * 2 pi hbar / max|V|).
+__device__ __forceinline__ double adapt_rule(const AdaptArgs& a, double vmax) {
+  double dt = fmin(a.dt_max, a.courant * a.dtk);
+  if (vmax > 0.0) dt = fmin(dt, a.courant * 6.283185307179586476925286766559 * a.hbar / vmax);
+  return dt;
+}
+
+__device__ __forceinline__ cx<double> drift_factor(const AdaptArgs& a, int axis, int j, double tau) {
+  const double arg = a.hbar * a.k2[axis][j] * tau * 0.5;
+  double sn, cs;
+  sincos(arg, &sn, &cs);
+  const double inv = 1.0 / (double)a.n[axis];
+  return {cs * inv, -sn * inv};
+}
+
+__global__ void adapt_kernel(AdaptArgs a) {
+  const int axis = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  double* S = a.st;
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (a.step < 0) {
+    const double d0 = adapt_rule(a, S[5]);  // steps 0 and 1 from the initial potential
+    if (j < a.n[axis]) {
+      a.tab[(size_t)(2 * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, 0.5 * d0);
+      a.tab[(size_t)(0 * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, a.last_next ? 0.5 * d0 : d0);
+    }
+    if (lead) {
+      S[0] = d0;
+      S[1] = d0;
+      S[3] = 0.0;
+      S[4] = 0.0;
+      S[6] = d0 / a.hbar;
+    }
+    return;
+  }
+  const int64_t n = a.step;
+  const double d1 = S[(n + 1) % 3];        // step n + 1
+  const double d2 = adapt_rule(a, S[3 + n % 3]);  // step n + 2, from the potential of step n
+  const int p = (int)((n + 1) % 2);
+  if (j < a.n[axis])
+    a.tab[(size_t)(p * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, a.last_next ? 0.5 * d1 : 0.5 * (d1 + d2));
+  if (lead) {
+    if (a.dt_out) a.dt_out[n] = S[n % 3];
+    S[(n + 2) % 3] = d2;
+    S[3 + (n + 1) % 3] = 0.0;
+    S[6 + p] = d1 / a.hbar;
+  }
+}
+
+__global__ void adapt_clear_kernel(double* st) {
+  if (threadIdx.x < 8) st[threadIdx.x] = 0.0;
+}
+
+hipError_t launch_adapt_clear(const Plan& P, hipStream_t s) {
+  hipLaunchKernelGGL(adapt_clear_kernel, dim3(1), dim3(64), 0, s, P.adapt);
+  return hipGetLastError();
+}
+
+hipError_t launch_adapt(const Plan& P, int64_t step, int last_next, double dt_max, double courant, double dtk,
+                        double* dt_out, hipStream_t s) {
+  AdaptArgs a;
+  a.st = P.adapt;
+  a.tab = reinterpret_cast<cx<double>*>(P.adapt_tab);
+  for (int d = 0; d < 3; ++d) {
+    a.k2[d] = P.k2[d];
+    a.n[d] = P.n[d];
+  }
+  a.dim = P.dim;
+  a.nmax = P.nmax;
+  a.hbar = P.p.hbar_m;
+  a.dt_max = dt_max;
+  a.courant = courant;
+  a.dtk = dtk;
+  a.step = step;
+  a.last_next = last_next;
+  a.dt_out = dt_out;
+  hipLaunchKernelGGL(adapt_kernel, dim3((unsigned)((P.nmax + 255) / 256), (unsigned)P.dim), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // mean density m_tot * sum_g |psi_g|^2 / N of every field, FP64.
 template <class T>
 __global__ void __launch_bounds__(256) field_mean_kernel(const void* psi, const void* psi_cl, int64_t n_real,

@@ -217,6 +217,17 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
       }
       inv(q, V[q]);
     }
+    if (a.vmax) {
+      double mx = 0.0;
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q)
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+          mx = fmax(mx, fmax(fabs((double)V[q][m].re), hasB ? fabs((double)V[q][m].im) : 0.0));
+      mx = block_max(mx, red);
+      if (tid == 0) record_max(a.vmax, mx);
+    }
+    const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
     for (int k = 0; k < 2; ++k) {
       const int64_t f = k == 0 ? fA : fB;
       if (k == 1 && !hasB) break;
@@ -232,7 +243,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         if constexpr (MODE == PASS_KICK_DRIFT) {
 #pragma unroll
           for (int m = 0; m < R; ++m) {
-            v[m] = cmul(v[m], expmi<T>(a.kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
+            v[m] = cmul(v[m], expmi<T>(kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
           }
           drift(q, v);
           pencil_put(q, v);

@@ -76,4 +76,25 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
+// Max of `x` over the workgroup, result valid in thread 0 (same layout as block_sum).
+__device__ __forceinline__ double block_max(double x, double* red) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+  }
+  return m;
+}
+
+// Running maximum of non-negative doubles: their bit patterns order like
+// unsigned integers, so an integer atomic max is exact and order-independent.
+__device__ __forceinline__ void record_max(double* dst, double m) {
+  atomicMax(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)__double_as_longlong(m));
+}
+
 }  // namespace tw

@@ -162,16 +162,24 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
     store(zp, zv);
   } else if constexpr (MODE == PASS_KICK_DRIFT) {
     fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+    if (a.vmax) {
+      double mx = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) mx = fmax(mx, fmax(fabs((double)zv[m].re), hasB ? fabs((double)zv[m].im) : 0.0));
+      mx = block_max(mx, red);
+      if (tid == 0) record_max(a.vmax, mx);
+    }
+    const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      va[m] = cmul(va[m], expmi<T>(a.kick * (double)zv[m].re));
+      va[m] = cmul(va[m], expmi<T>(kick * (double)zv[m].re));
     }
     drift(va);
     store_psi(fA, va);
     if (hasB) {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        vb[m] = cmul(vb[m], expmi<T>(a.kick * (double)zv[m].im));
+        vb[m] = cmul(vb[m], expmi<T>(kick * (double)zv[m].im));
       }
       drift(vb);
       store_psi(fB, vb);
@@ -201,6 +209,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       }
     }
     fft_pencil<T, N, true, SW>(zv, lds, t, tc);
+    if (a.vmax) {
+      double mx = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) mx = fmax(mx, fmax(fabs((double)zv[m].re), hasB ? fabs((double)zv[m].im) : 0.0));
+      mx = block_max(mx, red);
+      if (tid == 0) record_max(a.vmax, mx);
+    }
     for (int k = 0; k < 2; ++k) {
       if (k == 1 && !hasB) break;
       const cx<T>* v = k == 0 ? va : vb;

@@ -23,7 +23,7 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
                 "nonfinite", "energy_classical")
 
 # Exported entry points and their argument types (mirrors include/tw.h).
-EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_moments",
+EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_step_adaptive", "tw_moments",
            "tw_plan_autotune", "tw_batch_create", "tw_batch_plan", "tw_batch_autotune", "tw_batch_step",
            "tw_batch_destroy", "tw_fno_param_count", "tw_fno_create", "tw_fno_destroy", "tw_fno_init_params",
            "tw_fno_forward", "tw_fno_backward", "tw_fno_mse", "tw_fno_adam", "tw_fno_last_error",
@@ -66,6 +66,7 @@ def load_library(path=LIB_PATH):
     lib.tw_plan_destroy.argtypes = [vp]
     lib.tw_sample.argtypes = [vp, vp, u64, i64, vp, vp]
     lib.tw_step.argtypes = [vp, vp, vp, i64, dbl, vp]
+    lib.tw_step_adaptive.argtypes = [vp, vp, vp, i64, dbl, dbl, vp, vp]
     lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
     lib.tw_plan_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.tw_batch_create.argtypes = [ctypes.POINTER(TwProblem), ctypes.c_int32, ctypes.POINTER(vp)]
@@ -222,6 +223,18 @@ class Plan:
         _check(self._lib.tw_step(self.handle, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
                "tw_step")
         return psi
+
+    def step_adaptive(self, psi, nsteps, dt_max, courant=1.0, psi_classical=None):
+        """Advance psi (and psi_classical) in place by nsteps steps whose sizes the
+        device chooses (tw_step_adaptive). Returns the step sizes as a float64
+        device tensor [nsteps]."""
+        assert psi.dtype == self.problem.cdtype and psi.is_contiguous()
+        if psi_classical is not None:
+            assert psi_classical.dtype == self.problem.cdtype and psi_classical.is_contiguous()
+        dts = torch.zeros(max(int(nsteps), 1), dtype=torch.float64, device=psi.device)
+        _check(self._lib.tw_step_adaptive(self.handle, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt_max),
+                                          float(courant), _ptr(dts), _stream()), "tw_step_adaptive")
+        return dts[: int(nsteps)]
 
     def autotune(self):
         """Measure both strided-pass organisations and keep the faster (tw_plan_autotune)."""

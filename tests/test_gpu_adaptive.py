@@ -1,0 +1,97 @@
+"""Adaptive step sizes chosen on the device (tw_step_adaptive) against the
+oracle's adaptive evolution (same rule, same lag), and against tw_step where
+the rule reduces to a fixed step."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import twa_oracle as tw
+from paper_2310_07119_amd import Plan, Problem, inputs
+from tests.gpu_util import TOL, oracle_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("transpose", ["0", "1"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_free_field_equals_fixed_step(precision, transpose, monkeypatch):
+    """G = 0: the potential bound is idle and dt_max binds, so every step is
+    dt_max and the fields equal tw_step's bit for bit."""
+    monkeypatch.setenv("TW_TRANSPOSE", transpose)
+    p = Problem(n=(64, 32), box=(1.0, 0.5), hbar_m=0.8, G=0.0, n_tot=1e4, n_real=7, precision=precision)
+    psi_cl = inputs.lognormal_field(p.n, p.box, kcut=8, seed=2)
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    a = plan.sample(cl, 9)
+    b = a.clone()
+    ca = cl.to(p.cdtype).clone()
+    cb = ca.clone()
+    print(f"adaptive free field {precision} transpose={transpose}", flush=True)
+    dts = plan.step_adaptive(a, 5, 1e-3, courant=0.5, psi_classical=ca)
+    plan.step(b, 5, 1e-3, cb)
+    torch.cuda.synchronize()
+    assert torch.all(dts == 1e-3)
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+    plan.close()
+
+
+CASES = [
+    # (n, box, n_real, nsteps)
+    ((64, 32), (1.0, 0.5), 5, 8),
+    ((128, 128), (1.0, 1.0), 33, 6),
+    ((32, 16, 16), (1.0, 0.5, 0.5), 3, 5),
+]
+
+
+@pytest.mark.parametrize("transpose", ["0", "1"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])))
+def test_potential_bound_vs_oracle(case, precision, transpose, monkeypatch):
+    """Small hbar and strong gravity: the potential bound sets (and changes)
+    the step sizes. Fields and step sizes against the oracle, which takes the
+    maximum over the same fields (realizations and the classical one)."""
+    n, box, nr, nsteps = case
+    if len(n) == 3 and transpose == "1":
+        pytest.skip("the alternating schedule is the 2D one")
+    monkeypatch.setenv("TW_TRANSPOSE", transpose)
+    p = Problem(n=n, box=box, hbar_m=0.05, G=1.0, m_tot=30.0, n_tot=1e5, n_real=nr, precision=precision)
+    psi_cl = inputs.lognormal_field(n, box, kcut=min(n) // 4, seed=5)
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 77)
+    clt = cl.to(p.cdtype).clone()
+    psi0 = psi.cpu().numpy().astype(np.complex128)
+    print(f"adaptive {n} {precision} transpose={transpose}", flush=True)
+    dts = plan.step_adaptive(psi, nsteps, 1.0, courant=0.5, psi_classical=clt).cpu().numpy()
+    torch.cuda.synchronize()
+    prob = oracle_problem(p)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64).astype(np.complex128)
+    ref, rdts = tw.evolve_adaptive(prob, np.concatenate([psi0, cl0[None]]), nsteps, 1.0, 0.5)
+    assert len(set(rdts.tolist())) > 2, "the potential bound should bind and vary"
+    tol = TOL[precision]
+    assert rel(dts, rdts) < (1e-12 if precision == "fp64" else 1e-5)
+    assert rel(psi.cpu().numpy(), ref[:nr]) < tol
+    assert rel(clt.cpu().numpy(), ref[nr]) < tol
+    plan.close()
+
+
+def test_adaptive_rejects_bad_arguments():
+    from paper_2310_07119_amd.twa import TwError
+    p1 = Problem(n=(64,), n_real=2, n_tot=1e3)
+    plan = Plan(p1)
+    psi = torch.zeros((2, 64), dtype=torch.complex128, device="cuda")
+    with pytest.raises(TwError):
+        plan.step_adaptive(psi, 2, 1e-3)
+    p2 = Problem(n=(32, 32), n_real=2, n_tot=1e3)
+    plan2 = Plan(p2)
+    psi2 = torch.zeros((2, 32, 32), dtype=torch.complex128, device="cuda")
+    with pytest.raises(TwError):
+        plan2.step_adaptive(psi2, 2, 1e-3, courant=1.5)
+    with pytest.raises(TwError):
+        plan2.step_adaptive(psi2, 2, -1.0)

@@ -193,3 +193,57 @@ def test_time_reversal():
     back = tw.evolve(prob, fwd, 300, -1e-3)
     assert rel(back, psi0) < 1e-11
     assert rel(fwd, psi0) > 1e-2
+
+
+# ------------------------------------------------------------- adaptive step
+def test_adaptive_free_field_equals_fixed_step():
+    """With G = 0 the potential bound never binds, so the adaptive evolution is
+    the fixed-step one at min(dt_max, c_f * kinetic bound), exactly."""
+    grid = tw.Grid((32, 16), (1.0, 0.5))
+    prob = tw.Problem(grid, hbar_m=0.8, G=0.0)
+    psi = inputs.lognormal_field((32, 16), (1.0, 0.5), seed=3)[None]
+    got, dts = tw.evolve_adaptive(prob, psi, 4, 1e-3, 0.5)
+    assert np.all(dts == 1e-3)
+    assert np.array_equal(got, tw.evolve(prob, psi, 4, 1e-3))
+    big, dts = tw.evolve_adaptive(prob, psi, 2, 10.0, 0.5)
+    # kinetic bound: dt < 4 pi / (hbar k_max dk), k_max = pi / dx, dk = 2 pi / L, worst axis
+    kin = min(4 * np.pi / (0.8 * (np.pi * n / L) * (2 * np.pi / L)) for n, L in ((32, 1.0), (16, 0.5)))
+    assert abs(kin - 2 * 0.5 ** 2 / (np.pi * 16 * 0.8)) < 1e-15
+    assert np.allclose(dts, 0.5 * kin, rtol=1e-15, atol=0)
+
+
+def test_adaptive_potential_bound_closed_form():
+    """Uniform density plus a cosine: V = -4 pi G eps cos(k0 x) / k0^2 exactly
+    (the mean is removed), so the first step is c_f 2 pi hbar / max|V| with
+    max|V| from that closed form, when it is the tighter bound."""
+    n, L = 64, 1.0
+    grid = tw.Grid((n,), (L,))
+    hbar, G, m_tot, c = 0.02, 30.0, 1.0, 0.7
+    prob = tw.Problem(grid, hbar_m=hbar, G=G, m_tot=m_tot)
+    x = np.arange(n) * L / n
+    eps, k0 = 0.2, 2 * np.pi * 2 / L
+    rho = m_tot / L * (1 + eps * np.cos(k0 * x))
+    psi = np.sqrt(rho / m_tot).astype(complex)[None]
+    vmax = 4 * np.pi * G * (m_tot / L) * eps / k0 ** 2
+    _, dts = tw.evolve_adaptive(prob, psi, 1, 1.0, c)
+    expect = c * 2 * np.pi * hbar / vmax
+    assert expect < c * 2 * L * (L / n) / (np.pi * hbar)
+    assert abs(dts[0] - expect) < 1e-12 * expect
+
+
+def test_adaptive_lag_rule():
+    """Steps 0 and 1 share the size set by the initial potential; the size of
+    step n + 2 comes from the potential evaluated inside step n (recomputed
+    here with the fixed-step pieces at the returned sizes)."""
+    grid = tw.Grid((32,), (1.0,))
+    prob = tw.Problem(grid, hbar_m=0.05, G=1.0, m_tot=30.0)
+    psi0 = np.stack([inputs.lognormal_field((32,), (1.0,), seed=s) for s in (1, 2)])
+    _, dts = tw.evolve_adaptive(prob, psi0, 5, 1.0, 0.5)
+    assert dts[0] == dts[1]
+    assert len(set(dts.tolist())) > 2   # the potential bound binds and varies
+    psi = psi0
+    for n in range(3):
+        half = tw.drift(prob, psi, dts[n] / 2)
+        V = tw.potential(prob, tw.density(prob, half))
+        assert dts[n + 2] == min(1.0, 0.5 * tw.kinetic_dt_bound(prob), 0.5 * 2 * np.pi * 0.05 / np.abs(V).max())
+        psi = tw.step(prob, psi, dts[n])
