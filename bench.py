@@ -290,7 +290,11 @@ def main():
         log(f"fp32: {r32['value']:.4e}, errors {out['fp32_split']['err_vs_fp64']}")
     if not args.no_adaptive:
         out["adaptive"] = run_adaptive(wl, args.precision, args.steps, args.warmup)
-        out["adaptive"]["fixed_step_ms_per_step"] = main_run["ms_per_step"]
+        ad = out["adaptive"]
+        ad["fixed_step_ms_per_step"] = main_run["ms_per_step"]
+        # simulated time per wall second against the fixed-step run's
+        ad["speedup_per_simulated_time"] = (ad["simulated_time"] / (args.steps * ad["ms_per_step"])) / (
+            wl["dt"] / main_run["ms_per_step"])
         log(f"adaptive: {out['adaptive']}")
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)

@@ -142,6 +142,12 @@ typedef struct {
                          alpha_g = sqrt(n_tot dV) psi'_g (unitary DFT, occupation
                          units; Sec. "Quantum description"): at sampling time
                          <|a_j|^2> = |a_cl,j|^2 + 1/2. Averages realizations only */
+  double* var_amp;    /* [N] <(A - <A>)^2>_g of the amplitude A = |psi'| */
+  double* var_phase;  /* [N] <dphi^2>_g, dphi = arg(psi' conj<psi'>) in (-pi, pi] */
+  double* decoherence;/* [2]: Var A~ = sum_g dV <psi^dag psi> <dA^2>/<A>, Var phi~ =
+                         sum_g dV <psi^dag psi> <dphi^2>/(pi/sqrt 3) (Sec. "Large
+                         quantum corrections", Eqs. (varA), (varPhi)), with the
+                         normal-ordered <psi^dag psi> = <|psi'|^2> - 1/(2 n_tot dV) */
   double* norm;       /* [n_real] sum_g |psi'|^2 dV per realization */
   double* energy;     /* [n_real] m_tot [ (hbar^2/2) int|grad psi'|^2 + (1/2) int V|psi'|^2 ] */
   double* scalars;    /* [8]: Q_raw, Q_sym, dev_rho_L1, dev_psi_L2, energy_mean,

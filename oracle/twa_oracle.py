@@ -287,7 +287,34 @@ def mode_amplitudes(prob, psi, n_tot):
     return prob.T.fwd(alpha) / np.sqrt(g.ncell)
 
 
-def moments(prob, psi, n_tot, psi_cl=None, modes=False):
+def decoherence(prob, psi, n_tot):
+    """Amplitude and phase spread of the ensemble (Sec. "Large quantum
+    corrections", Eqs. (varA) and (varPhi)). Per cell: the plug-in variance of
+    the amplitude A = |psi'| and of the phase deviation dphi = arg(psi'
+    conj<psi'>) in (-pi, pi] from the phase of the ensemble-mean field; the
+    integrals weight them with the normal-ordered density <psi^dag psi> =
+    <|psi'|^2> - 1/(2 n_tot dV) (the Weyl average minus the vacuum half quantum
+    per cell mode):
+        Var A~   = sum_g dV <psi^dag psi> <dA^2> / <A>
+        Var phi~ = sum_g dV <psi^dag psi> <dphi^2> / (pi / sqrt 3)
+    (the constant as printed; a uniformly random phase has <dphi^2> = pi^2/3).
+    Returns (var_amp, var_phase, Var_A, Var_phi)."""
+    g = prob.grid
+    ns = psi.shape[0]
+    amp = np.abs(psi)
+    mean_amp = amp.sum(axis=0) / ns
+    var_amp = ((amp - mean_amp[None]) ** 2).sum(axis=0) / ns
+    m1 = psi.sum(axis=0) / ns
+    dphi = np.angle(psi * np.conj(m1)[None])
+    var_phase = (dphi ** 2).sum(axis=0) / ns
+    occ = (psi.real ** 2 + psi.imag ** 2).sum(axis=0) / ns - 1.0 / (2.0 * n_tot * g.dV)
+    safe = np.where(mean_amp > 0, mean_amp, 1.0)
+    var_a = (g.dV * occ * np.where(mean_amp > 0, var_amp / safe, 0.0)).sum()
+    var_p = (g.dV * occ * var_phase).sum() / (np.pi / np.sqrt(3.0))
+    return var_amp, var_phase, float(var_a), float(var_p)
+
+
+def moments(prob, psi, n_tot, psi_cl=None, modes=False, decoherence_=False):
     """Ensemble moments by the plug-in estimator (1/N_s) sum_i (Sec. "Evaluating
     operators"); every Weyl symbol is evaluated per realization and averaged.
 
@@ -303,6 +330,7 @@ def moments(prob, psi, n_tot, psi_cl=None, modes=False):
       dev_psi_L2 sum_g dV |<psi'> - psi'_cl|^2               (if psi_cl given)
       nonfinite  count of realizations holding a non-finite value
       mode_occ   <|a_j|^2> per Fourier mode, a_j from mode_amplitudes (if modes=True)
+      var_amp, var_phase, Var_A, Var_phi   from `decoherence` (if decoherence_=True)
     """
     g = prob.grid
     ns = psi.shape[0]
@@ -319,6 +347,8 @@ def moments(prob, psi, n_tot, psi_cl=None, modes=False):
                Q_raw=q_raw, Q_sym=q_raw - g.ncell / (2.0 * n_tot))
     flat = psi.reshape(ns, -1)
     out["nonfinite"] = int((~np.isfinite(flat)).any(axis=1).sum())
+    if decoherence_:
+        out["var_amp"], out["var_phase"], out["Var_A"], out["Var_phi"] = decoherence(prob, psi, n_tot)
     if modes:
         a = mode_amplitudes(prob, psi, n_tot)
         out["mode_occ"] = (a.real ** 2 + a.imag ** 2).sum(axis=0) / ns

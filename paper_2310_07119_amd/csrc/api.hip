@@ -244,7 +244,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
     // the sizes of steps 0 and 1 and their drift tables
     TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_adapt_clear(P, s); }));
     PassArgs b = a;
-    b.vmax = P.adapt + 5;
+    b.vmax = P.adapt + kAdaptScalars + 2 * kVmaxBuckets;
     b.partial = P.partial;
     TW_HIP(pass(P, b, PASS_RHO, 0, nullptr, s));
     for (int d = 1; d < D - 1; ++d) TW_HIP(pass(P, b, PASS_ZFWD, d, nullptr, s));
@@ -259,7 +259,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   auto kick_args = [&](PassArgs& b, int64_t st) {
     if (!ad) return;
     b.kick_dev = P.adapt + 6 + st % 2;
-    b.vmax = P.adapt + 3 + st % 3;
+    b.vmax = P.adapt + kAdaptScalars + (st % 3) * kVmaxBuckets;
   };
   auto after_kick = [&](int64_t st) -> hipError_t {
     if (!ad) return hipSuccess;
@@ -517,12 +517,12 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
     }
   const int64_t nwaves = (P->ncell + 63) / 64;
   const int64_t energy_part = 4 * P->nfield * gmax + P->nfield;
-  const int64_t mom_part = pr->n_real * nwaves + 3 * nwaves + pr->n_real + 8;
+  const int64_t mom_part = pr->n_real * nwaves + 3 * nwaves + pr->n_real + 8 + 2 * nwaves;
   P->partial_len = (size_t)(energy_part + mom_part);
   ALLOC(P->partial, sizeof(double) * P->partial_len);
   ALLOC(P->scratch_small, sizeof(double) * 64);
   if (pr->dim >= 2) {
-    ALLOC(P->adapt, sizeof(double) * 16);
+    ALLOC(P->adapt, sizeof(double) * (kAdaptScalars + 3 * kVmaxBuckets));
     ALLOC(P->adapt_tab, sizeof(double) * 2 * 3 * 3 * (size_t)P->nmax);
   }
 #undef ALLOC
@@ -632,6 +632,15 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_cl, const tw_momen
       for (int d = 0; d < P.dim; ++d) TW_HIP(pass(P, a, PASS_ZFWD, d, nullptr, s));
       TW_HIP(timed(P, KIND_MODES, s, [&] { return launch_mode_occ(P, nslots, k, out->mode_occ, s); }));
     }
+  }
+  if (out->var_amp || out->var_phase || out->decoherence) {
+    // after the moment reductions' own region
+    const int64_t nwaves = (P.ncell + 63) / 64;
+    double* scratch = P.partial + 4 * P.nfield * partial_gmax(P) + P.nfield + P.p.n_real * nwaves + 3 * nwaves +
+                      P.p.n_real + 8;
+    TW_HIP(timed(P, KIND_MODES, s, [&] {
+      return launch_decoherence(P, psi, out->var_amp, out->var_phase, out->decoherence, scratch, s);
+    }));
   }
   Plan Q = P;
   // the moment reductions use the region after the energy partials

@@ -46,18 +46,50 @@ __device__ __forceinline__ cx<T> mul_d(cx<T> a, double f) {
   return {(T)((double)a.re * f), (T)((double)a.im * f)};
 }
 
-// exp(-i * arg) for an FP64 argument. FP64 storage: FP64 sine and cosine.
-// FP32 storage: the argument is reduced modulo 2 pi in FP64 and the reduced
-// angle is evaluated in FP32. Kick phases are small (|dt V / hbar| << 1), so
-// both first try Taylor series of sin and cos on |x| <= pi/4, where the
-// truncated terms are below one unit in the last place (FP64: through x^17 and
-// x^16; FP32: through x^9 and x^10); larger arguments take the library call.
+// exp(-i * arg) for an FP64 argument, in both storage precisions.
+//
+// The argument is reduced by quarter turns, arg = k pi/2 + r with |r| <= pi/4,
+// using pi/2 split into three parts (the first two with 33 significant bits,
+// so k * part is exact for |k| < 2^20: Cody and Waite's reduction). sin r and
+// cos r are Taylor series, truncated where the next term is below one unit in
+// the last place of the storage precision (FP64: through r^17 and r^16; FP32:
+// through r^9 and r^10), and the quadrant k mod 4 maps them to sin and cos of
+// arg. Arguments beyond 10^6 (never reached by kick phases) take the library
+// sincos.
+__device__ __forceinline__ bool quarter_turns(double arg, double& r, int& q) {
+  if (fabs(arg) <= 0.78539816339744830962) {  // already reduced (the common case: small kick phases)
+    r = arg;
+    q = 0;
+    return true;
+  }
+  if (!(fabs(arg) <= 1.0e6)) return false;
+  const double k = rint(arg * 0.63661977236758134308);  // 2/pi
+  r = ((arg - k * 1.5707963267341256) - k * 6.077100506303966e-11) - k * 2.0222662487959506e-21;
+  q = (int)((long long)k & 3);
+  return true;
+}
+
+// (cos, sin) of the reduced angle mapped to the quadrant: returns exp(-i arg).
+template <class T>
+__device__ __forceinline__ cx<T> quadrant(T c, T s, int q) {
+  T cosx, sinx;
+  switch (q) {
+    case 0: cosx = c; sinx = s; break;
+    case 1: cosx = -s; sinx = c; break;
+    case 2: cosx = -c; sinx = -s; break;
+    default: cosx = s; sinx = -c; break;
+  }
+  return {cosx, -sinx};
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> expmi(double arg);
 template <>
 __device__ __forceinline__ cx<double> expmi<double>(double arg) {
-  if (fabs(arg) <= 0.78539816339744830962) {
-    const double x2 = arg * arg;
+  double x;
+  int q;
+  if (quarter_turns(arg, x, q)) {
+    const double x2 = x * x;
     double ps = -1.0 / 355687428096000.0;
     ps = ps * x2 + 1.0 / 1307674368000.0;
     ps = ps * x2 - 1.0 / 6227020800.0;
@@ -74,9 +106,9 @@ __device__ __forceinline__ cx<double> expmi<double>(double arg) {
     pc = pc * x2 - 1.0 / 720.0;
     pc = pc * x2 + 1.0 / 24.0;
     pc = pc * x2 - 0.5;
-    const double s = arg - arg * x2 * ps;
+    const double s = x - x * x2 * ps;
     const double c = 1.0 + x2 * pc;
-    return {c, -s};
+    return quadrant<double>(c, s, q);
   }
   double s, c;
   sincos(arg, &s, &c);
@@ -84,8 +116,10 @@ __device__ __forceinline__ cx<double> expmi<double>(double arg) {
 }
 template <>
 __device__ __forceinline__ cx<float> expmi<float>(double arg) {
-  if (fabs(arg) <= 0.78539816339744830962) {
-    const float x = (float)arg, x2 = x * x;
+  double xr;
+  int q;
+  if (quarter_turns(arg, xr, q)) {
+    const float x = (float)xr, x2 = x * x;
     float ps = 1.f / 362880.f;
     ps = ps * x2 - 1.f / 5040.f;
     ps = ps * x2 + 1.f / 120.f;
@@ -95,7 +129,7 @@ __device__ __forceinline__ cx<float> expmi<float>(double arg) {
     pc = pc * x2 - 1.f / 720.f;
     pc = pc * x2 + 1.f / 24.f;
     pc = pc * x2 - 0.5f;
-    return {1.f + x2 * pc, -(x + x * x2 * ps)};
+    return quadrant<float>(1.f + x2 * pc, x + x * x2 * ps, q);
   }
   const double two_pi = 6.283185307179586476925286766559;
   double r = arg - two_pi * rint(arg * (1.0 / two_pi));

@@ -9,6 +9,9 @@
 namespace tw {
 
 // Arguments of one pencil pass over the ensemble (see kernels_step.hip).
+constexpr int kVmaxBuckets = 64;     // atomic-max slots per recorded maximum
+constexpr int kAdaptScalars = 16;    // adaptive-step state before the max|V| buckets
+
 struct PassArgs {
   void* psi;               // [n_real][N] fields (plan precision)
   void* psi_cl;            // extra classical field or nullptr
@@ -34,7 +37,7 @@ struct PassArgs {
   void* psi_t;             // destination of transposed field stores (never the buffer being read)
   void* psi_cl_t;          // ... its classical-field slot
   const double* kick_dev;  // PASS_KICK_DRIFT: kick factor dt/hbar read from device memory (overrides kick)
-  double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V| (atomic max on the bits)
+  double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V|, kVmaxBuckets slots (atomic max on the bits)
 };
 
 enum PassMode : int {
@@ -74,7 +77,7 @@ struct Plan {
   double* partial;       // reductions
   size_t partial_len;    // doubles
   double* scratch_small; // [64] misc device scalars
-  double* adapt;         // [16] adaptive-step state: dt ring [3], max|V| slots [3], kick factors [2]
+  double* adapt;         // adaptive-step state: dt ring [3], kick factors [2], then 3 x kVmaxBuckets max|V| slots
   void* adapt_tab;       // cx<double>[3][3][nmax]: drift tables of the adaptive schedule
   int64_t chunk_pairs;   // pairs advanced through all steps together (cache residency)
   int transpose2d;       // 2D steps use the alternating-storage row schedule
@@ -92,7 +95,7 @@ enum KernelKind : int {
   KIND_TABLES = 12,
   KIND_MEAN = 13,
   KIND_ENERGY = 14,
-  KIND_MODES = 15,
+  KIND_MODES = 15,  // mode occupations and the amplitude/phase spread
   KIND_COUNT = 16
 };
 
@@ -117,6 +120,8 @@ hipError_t launch_sample(const Plan& P, const void* psi_cl, uint64_t seed, int64
 hipError_t launch_energy_finalize(const Plan& P, const double* partial, int64_t gstride, int64_t nfield,
                                   const int ng[4], double* out, hipStream_t s);
 hipError_t launch_gather_round(const Plan& P, const void* psi, int64_t nslots, int k, hipStream_t s);
+hipError_t launch_decoherence(const Plan& P, const void* psi, double* var_amp, double* var_phase, double* integrals,
+                              double* scratch, hipStream_t s);
 hipError_t launch_mode_occ(const Plan& P, int64_t nslots, int accumulate, double* occ, hipStream_t s);
 hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
                           const double* energy_dev, hipStream_t s);

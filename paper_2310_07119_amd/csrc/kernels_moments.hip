@@ -263,4 +263,98 @@ hipError_t launch_mode_occ(const Plan& P, int64_t nslots, int accumulate, double
   return hipGetLastError();
 }
 
+// Amplitude and phase spread of the ensemble (Sec. "Large quantum
+// corrections", Eqs. (varA) and (varPhi)): per cell the plug-in variances of
+// A = |psi'| and of the phase deviation dphi = arg(psi' conj<psi'>) in
+// (-pi, pi], weighted by the normal-ordered density <psi^dag psi> =
+// <|psi'|^2> - 1/(2 n_tot dV) and integrated over the box:
+//   Var A~   = sum_g dV <psi^dag psi> <dA^2> / <A>
+//   Var phi~ = sum_g dV <psi^dag psi> <dphi^2> / (pi / sqrt 3).
+// Two passes over the realizations per cell (means first, then deviations).
+struct DecoArgs {
+  const void* psi;
+  int64_t n_real;
+  int64_t ncell;
+  double dV;
+  double vac;  // 1 / (2 n_tot dV): Weyl minus normal ordering per cell
+  double* var_amp;
+  double* var_phase;
+  double* wave_d;  // [2][nwaves]
+  int64_t nwaves;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) decoherence_kernel(DecoArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = g < a.ncell;
+  const int64_t wave = g >> 6;
+  const int lane = threadIdx.x & 63;
+  const cx<T>* psi = reinterpret_cast<const cx<T>*>(a.psi);
+  const double inv = 1.0 / (double)a.n_real;
+  cx<double> s1 = {0.0, 0.0};
+  double s2 = 0.0, sa = 0.0;
+  if (active) {
+    for (int64_t r = 0; r < a.n_real; ++r) {
+      const cx<T> w = psi[r * a.ncell + g];
+      const cx<double> v = {(double)w.re, (double)w.im};
+      const double a2 = v.re * v.re + v.im * v.im;
+      s1 = s1 + v;
+      s2 += a2;
+      sa += sqrt(a2);
+    }
+  }
+  const cx<double> m1 = {s1.re * inv, s1.im * inv};
+  const double ma = sa * inv;
+  double va = 0.0, vp = 0.0;
+  if (active) {
+    for (int64_t r = 0; r < a.n_real; ++r) {
+      const cx<T> w = psi[r * a.ncell + g];
+      const cx<double> v = {(double)w.re, (double)w.im};
+      const double da = sqrt(v.re * v.re + v.im * v.im) - ma;
+      va += da * da;
+      const cx<double> u = cmulc(v, m1);
+      const double ph = atan2(u.im, u.re);
+      vp += ph * ph;
+    }
+  }
+  va *= inv;
+  vp *= inv;
+  double ia = 0.0, ip = 0.0;
+  if (active) {
+    if (a.var_amp) a.var_amp[g] = va;
+    if (a.var_phase) a.var_phase[g] = vp;
+    const double occ = s2 * inv - a.vac;
+    ia = ma > 0.0 ? a.dV * occ * va / ma : 0.0;
+    ip = a.dV * occ * vp / (3.14159265358979323846 / sqrt(3.0));
+  }
+  ia = wave_sum(ia);
+  ip = wave_sum(ip);
+  if (lane == 0 && wave < a.nwaves) {
+    a.wave_d[wave] = ia;
+    a.wave_d[a.nwaves + wave] = ip;
+  }
+}
+
+hipError_t launch_decoherence(const Plan& P, const void* psi, double* var_amp, double* var_phase, double* integrals,
+                              double* scratch, hipStream_t s) {
+  const int64_t nwaves = (P.ncell + 63) / 64;
+  DecoArgs a;
+  a.psi = psi;
+  a.n_real = P.p.n_real;
+  a.ncell = P.ncell;
+  a.dV = P.dV;
+  a.vac = 1.0 / (2.0 * P.p.n_tot * P.dV);
+  a.var_amp = var_amp;
+  a.var_phase = var_phase;
+  a.wave_d = scratch;
+  a.nwaves = nwaves;
+  dim3 grid((unsigned)((P.ncell + 255) / 256));
+  if (P.fp32) hipLaunchKernelGGL(decoherence_kernel<float>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(decoherence_kernel<double>, grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !integrals) return e;
+  hipLaunchKernelGGL(row_sum_kernel, dim3(2), dim3(256), 0, s, scratch, nwaves, 1.0, integrals);
+  return hipGetLastError();
+}
+
 }  // namespace tw

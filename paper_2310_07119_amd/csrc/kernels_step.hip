@@ -230,9 +230,10 @@ hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hi
 }
 
 // ------------------------------------------------------- adaptive step
-// State (doubles): [0..2] step sizes dt_n at slot n mod 3; [3..5] running
-// max |V| recorded by the kick pass of step n at slot 3 + n mod 3 (slot 5 also
-// holds the initial potential's); [6..7] kick factor dt_n / hbar at 6 + n mod 2.
+// State (doubles): [0..2] step sizes dt_n at slot n mod 3; [6..7] kick factor
+// dt_n / hbar at 6 + n mod 2; from kAdaptScalars on, three groups of
+// kVmaxBuckets running max |V| values: the kick pass of step n records into
+// group n mod 3 (group 2 also holds the initial potential's).
 // Drift tables: adapt_tab[p][axis] for steps of parity p, adapt_tab[2][axis]
 // for the opening half drift.
 struct AdaptArgs {
@@ -263,13 +264,21 @@ __device__ __forceinline__ cx<double> drift_factor(const AdaptArgs& a, int axis,
   return {cs * inv, -sn * inv};
 }
 
+__device__ __forceinline__ double bucket_max(const double* b) {
+  double m = 0.0;
+  for (int i = 0; i < kVmaxBuckets; ++i) m = fmax(m, b[i]);
+  return m;
+}
+
 __global__ void adapt_kernel(AdaptArgs a) {
   const int axis = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   double* S = a.st;
-  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  double* buckets = S + kAdaptScalars;
+  const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+  const bool lead = lead_block && threadIdx.x == 0;
   if (a.step < 0) {
-    const double d0 = adapt_rule(a, S[5]);  // steps 0 and 1 from the initial potential
+    const double d0 = adapt_rule(a, bucket_max(buckets + 2 * kVmaxBuckets));  // steps 0 and 1
     if (j < a.n[axis]) {
       a.tab[(size_t)(2 * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, 0.5 * d0);
       a.tab[(size_t)(0 * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, a.last_next ? 0.5 * d0 : d0);
@@ -277,32 +286,31 @@ __global__ void adapt_kernel(AdaptArgs a) {
     if (lead) {
       S[0] = d0;
       S[1] = d0;
-      S[3] = 0.0;
-      S[4] = 0.0;
       S[6] = d0 / a.hbar;
     }
+    // groups 0 and 1 were cleared with the state; group 2 is read above
     return;
   }
   const int64_t n = a.step;
-  const double d1 = S[(n + 1) % 3];        // step n + 1
-  const double d2 = adapt_rule(a, S[3 + n % 3]);  // step n + 2, from the potential of step n
+  const double d1 = S[(n + 1) % 3];                                     // step n + 1
+  const double d2 = adapt_rule(a, bucket_max(buckets + (n % 3) * kVmaxBuckets));  // step n + 2
   const int p = (int)((n + 1) % 2);
   if (j < a.n[axis])
     a.tab[(size_t)(p * 3 + axis) * a.nmax + j] = drift_factor(a, axis, j, a.last_next ? 0.5 * d1 : 0.5 * (d1 + d2));
+  if (lead_block && threadIdx.x < kVmaxBuckets) buckets[((n + 1) % 3) * kVmaxBuckets + threadIdx.x] = 0.0;
   if (lead) {
     if (a.dt_out) a.dt_out[n] = S[n % 3];
     S[(n + 2) % 3] = d2;
-    S[3 + (n + 1) % 3] = 0.0;
     S[6 + p] = d1 / a.hbar;
   }
 }
 
-__global__ void adapt_clear_kernel(double* st) {
-  if (threadIdx.x < 8) st[threadIdx.x] = 0.0;
+__global__ void adapt_clear_kernel(double* st, int len) {
+  for (int i = threadIdx.x; i < len; i += blockDim.x) st[i] = 0.0;
 }
 
 hipError_t launch_adapt_clear(const Plan& P, hipStream_t s) {
-  hipLaunchKernelGGL(adapt_clear_kernel, dim3(1), dim3(64), 0, s, P.adapt);
+  hipLaunchKernelGGL(adapt_clear_kernel, dim3(1), dim3(256), 0, s, P.adapt, kAdaptScalars + 3 * kVmaxBuckets);
   return hipGetLastError();
 }
 

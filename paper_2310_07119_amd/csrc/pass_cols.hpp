@@ -225,7 +225,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         for (int m = 0; m < R; ++m)
           mx = fmax(mx, fmax(fabs((double)V[q][m].re), hasB ? fabs((double)V[q][m].im) : 0.0));
       mx = block_max(mx, red);
-      if (tid == 0) record_max(a.vmax, mx);
+      if (tid == 0) record_max(a.vmax + ((bx + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
     for (int k = 0; k < 2; ++k) {

@@ -93,6 +93,9 @@ __device__ __forceinline__ double block_max(double x, double* red) {
 
 // Running maximum of non-negative doubles: their bit patterns order like
 // unsigned integers, so an integer atomic max is exact and order-independent.
+// Workgroups spread their updates over kVmaxBuckets addresses (one address
+// for a whole pass serialises thousands of atomics); readers take the max of
+// the buckets.
 __device__ __forceinline__ void record_max(double* dst, double m) {
   atomicMax(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)__double_as_longlong(m));
 }

@@ -167,7 +167,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
       for (int m = 0; m < R; ++m) mx = fmax(mx, fmax(fabs((double)zv[m].re), hasB ? fabs((double)zv[m].im) : 0.0));
       mx = block_max(mx, red);
-      if (tid == 0) record_max(a.vmax, mx);
+      if (tid == 0) record_max(a.vmax + ((bx + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
 #pragma unroll
@@ -214,7 +214,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
 #pragma unroll
       for (int m = 0; m < R; ++m) mx = fmax(mx, fmax(fabs((double)zv[m].re), hasB ? fabs((double)zv[m].im) : 0.0));
       mx = block_max(mx, red);
-      if (tid == 0) record_max(a.vmax, mx);
+      if (tid == 0) record_max(a.vmax + ((bx + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
     for (int k = 0; k < 2; ++k) {
       if (k == 1 && !hasB) break;

@@ -123,6 +123,40 @@ def random_field(n, seed=0):
     return psi
 
 
+def sinusoid(n, box, delta=0.1):
+    """The sinusoidal overdensity test problem (Sec. "Sinusoidal overdensity"):
+    psi_cl = sqrt(1 + delta cos(2 pi x / L_x)), normalised; constant along
+    the other axes."""
+    x = _grid_coords(n, box)[0]
+    shape = tuple(reversed(tuple(int(v) for v in n)))
+    psi = np.broadcast_to(np.sqrt(1.0 + delta * np.cos(2.0 * np.pi * x / box[0])), shape).astype(np.complex128)
+    return normalise(psi, n, box)
+
+
+def kspace_gaussian(n, box, kd, seed=0):
+    """The momentum-space Gaussian test problem (Sec. "Momentum space
+    gaussian", Eq. (kspaceGauss)): Fourier amplitudes exp(-|k|^2 / (2 kd^2))
+    with independent uniform phases on every mode, transformed to position
+    space and normalised. The printed phase distribution U[0, 1] is read as a
+    full turn, U[0, 2 pi)."""
+    dim = len(n)
+    shape = tuple(reversed(tuple(int(v) for v in n)))
+    k2 = np.zeros(shape)
+    for d in range(dim):
+        k = 2.0 * np.pi * np.fft.fftfreq(n[d], d=box[d] / n[d])
+        sh = [1] * dim
+        sh[dim - 1 - d] = n[d]
+        k2 = k2 + (k ** 2).reshape(sh)
+    rng = np.random.default_rng(seed)
+    phase = rng.uniform(0.0, 2.0 * np.pi, shape)
+    psi = np.fft.ifftn(np.exp(-k2 / (2.0 * kd ** 2) + 1j * phase))
+    return normalise(psi, n, box)
+
+
+# Gravitational constant in kpc^3 / (M_sun Myr^2) (GM_sun = 1.32712440018e20
+# m^3/s^2, 1 kpc = 3.0856775814913673e19 m, 1 Myr = 3.15576e13 s).
+G_KPC_MYR_MSUN = 4.4985021520796915e-12
+
 # Named workloads --------------------------------------------------------------
 WORKLOADS = {
     "1d_n256": dict(n=(256,), box=(1.0,), n_real=64, n_tot=1e4, dt=1e-4, nsteps=1000,
@@ -134,6 +168,14 @@ WORKLOADS = {
     # three size classes advanced together (FP32 split): 64 realizations each
     "3d_batched_soliton": dict(classes=((64, 64, 64), (96, 96, 96), (128, 128, 128)), box=(1.0, 1.0, 1.0),
                                n_real=64, occupation=1e3, dt=1e-4, nsteps=1000, hbar_m=1.0, G=1.0, m_tot=1.0),
+    # the paper's own test problems in its physical units (kpc, Myr, M_sun), run
+    # with device-chosen steps (dt is the upper bound dt_max)
+    "1d_sinusoid": dict(n=(512,), box=(60.0,), n_real=64, n_tot=1e6, dt=10.0, nsteps=1000, hbar_m=0.01,
+                        G=G_KPC_MYR_MSUN, m_tot=1e8, delta=0.1),
+    "2d_n512_kgauss": dict(n=(512, 512), box=(60.0, 60.0), n_real=64, n_tot=1e3 * 512 ** 2, dt=10.0, nsteps=1000,
+                           hbar_m=0.02, G=G_KPC_MYR_MSUN, m_tot=6e9, kd=0.158113883008419),
+    "3d_n512_kgauss": dict(n=(512, 512, 512), box=(60.0, 60.0, 60.0), n_real=32, n_tot=1e3 * 512 ** 3, dt=10.0,
+                           nsteps=1000, hbar_m=0.02, G=G_KPC_MYR_MSUN, m_tot=1e10, kd=0.158113883008419),
 }
 
 
@@ -150,4 +192,8 @@ def initial_field(name, n=None):
         return lognormal_field(n, box, kcut=min(32, min(n) // 2), seed=0)
     if name == "3d_batched_soliton":
         return soliton_3d(n, box, core=0.1)
+    if name == "1d_sinusoid":
+        return sinusoid(n, box, w["delta"])
+    if name in ("2d_n512_kgauss", "3d_n512_kgauss"):
+        return kspace_gaussian(n, box, w["kd"], seed=1)
     raise KeyError(name)

@@ -40,7 +40,8 @@ class TwProblem(ctypes.Structure):
 
 class TwMomentsOut(ctypes.Structure):
     _fields_ = [("mean_psi", ctypes.c_void_p), ("mean_abs2", ctypes.c_void_p), ("mean_rho", ctypes.c_void_p),
-                ("var_rho", ctypes.c_void_p), ("mode_occ", ctypes.c_void_p), ("norm", ctypes.c_void_p),
+                ("var_rho", ctypes.c_void_p), ("mode_occ", ctypes.c_void_p), ("var_amp", ctypes.c_void_p),
+                ("var_phase", ctypes.c_void_p), ("decoherence", ctypes.c_void_p), ("norm", ctypes.c_void_p),
                 ("energy", ctypes.c_void_p), ("scalars", ctypes.c_void_p)]
 
 
@@ -258,9 +259,11 @@ class Plan:
                 out[self._lib.tw_kernel_kind_name(k).decode()] = (int(launches[k]), float(ms[k]))
         return out
 
-    def moments(self, psi, psi_classical=None, energy=True, per_cell=True, modes=False):
+    def moments(self, psi, psi_classical=None, energy=True, per_cell=True, modes=False, decoherence=False):
         """Ensemble moments (tw_moments) as a dict of device tensors (scalars on the host).
-        modes=True adds mode_occ, the per-mode occupation <|a_j|^2>."""
+        modes=True adds mode_occ, the per-mode occupation <|a_j|^2>; decoherence=True
+        adds the per-cell amplitude and phase variances var_amp, var_phase and the
+        weighted integrals Var_A, Var_phi."""
         p = self.problem
         dev = psi.device
         f64 = dict(dtype=torch.float64, device=dev)
@@ -274,10 +277,17 @@ class Plan:
             out["energy"] = torch.empty(p.n_real, **f64)
         if modes:
             out["mode_occ"] = torch.empty(p.shape, **f64)
+        deco = None
+        if decoherence:
+            out["var_amp"] = torch.empty(p.shape, **f64)
+            out["var_phase"] = torch.empty(p.shape, **f64)
+            deco = torch.empty(2, **f64)
         scal = torch.empty(8, **f64)
         mo = TwMomentsOut()
-        for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "mode_occ", "norm", "energy"):
+        for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "mode_occ", "var_amp", "var_phase", "norm",
+                  "energy"):
             setattr(mo, k, out[k].data_ptr() if k in out else None)
+        mo.decoherence = deco.data_ptr() if deco is not None else None
         mo.scalars = scal.data_ptr()
         _check(self._lib.tw_moments(self.handle, _ptr(psi), _ptr(psi_classical), ctypes.byref(mo), _stream()),
                "tw_moments")
@@ -285,6 +295,8 @@ class Plan:
         for name, v in zip(SCALAR_NAMES, vals):
             out[name] = v
         out["nonfinite"] = int(out["nonfinite"])
+        if deco is not None:
+            out["Var_A"], out["Var_phi"] = deco.cpu().tolist()
         return out
 
 

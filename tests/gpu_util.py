@@ -21,7 +21,8 @@ def oracle_problem(p: Problem):
     return tw.Problem(grid, p.hbar_m, p.G, p.m_tot)
 
 
-def gpu_run(p: Problem, psi_cl_np, seed, nsteps, dt, real_offset=0, with_classical=True, energy=True, modes=False):
+def gpu_run(p: Problem, psi_cl_np, seed, nsteps, dt, real_offset=0, with_classical=True, energy=True, modes=False,
+            decoherence=False):
     """Sample, step and take moments on the GPU; returns host numpy results."""
     dev = torch.device("cuda:0")
     plan = Plan(p)
@@ -30,7 +31,7 @@ def gpu_run(p: Problem, psi_cl_np, seed, nsteps, dt, real_offset=0, with_classic
     psi0 = psi.cpu().numpy()
     clt = cl.to(p.cdtype).clone() if with_classical else None
     plan.step(psi, nsteps, dt, clt)
-    mom = plan.moments(psi, clt, energy=energy, modes=modes)
+    mom = plan.moments(psi, clt, energy=energy, modes=modes, decoherence=decoherence)
     torch.cuda.synchronize()
     out = dict(psi0=psi0, psi=psi.cpu().numpy(), cl=None if clt is None else clt.cpu().numpy())
     out["mom"] = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in mom.items()}

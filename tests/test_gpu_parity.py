@@ -44,7 +44,7 @@ def test_sample_step_moments_vs_oracle(case, precision, variant, monkeypatch):
     psi_cl = inputs.lognormal_field(n, p.box, kcut=min(n) // 4, seed=1)
     seed = 1234567
     print(f"case n={n} n_real={nr} {precision}", flush=True)
-    g = gpu_run(p, psi_cl, seed, nsteps, dt, real_offset=7, modes=True)
+    g = gpu_run(p, psi_cl, seed, nsteps, dt, real_offset=7, modes=True, decoherence=True)
     prob = oracle_problem(p)
     psi0 = tw.sample(prob.grid, psi_cl, nr, n_tot, seed, real_offset=7)
     # sampled initial state: bit-exact (FP32 = the FP64 draw rounded to nearest)
@@ -59,11 +59,11 @@ def test_sample_step_moments_vs_oracle(case, precision, variant, monkeypatch):
     tol = TOL[precision]
     assert rel(g["psi"], psi) < tol
     assert rel(g["cl"], cl) < tol
-    ref = tw.moments(prob, psi, n_tot, cl, modes=True)
+    ref = tw.moments(prob, psi, n_tot, cl, modes=True, decoherence_=True)
     m = g["mom"]
-    for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "mode_occ", "norm", "energy"):
+    for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "mode_occ", "var_amp", "var_phase", "norm", "energy"):
         assert rel(m[k], ref[k]) < tol * 10, k
-    for k in ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2"):
+    for k in ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "Var_A", "Var_phi"):
         assert abs(m[k] - ref[k]) <= tol * 10 * max(abs(ref[k]), 1e-300) + 1e-300, k
     assert abs(m["energy_mean"] - ref["energy"].mean()) < tol * 10 * abs(ref["energy"].mean())
     assert abs(m["energy_classical"] - tw.energy(prob, cl)) < tol * 10 * abs(tw.energy(prob, cl))

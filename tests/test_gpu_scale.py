@@ -1,0 +1,83 @@
+"""The paper's momentum-space Gaussian test problem at 512^3 (FP32 split, the
+largest grid the passes support), and the same family regenerated at 32^3 for
+a complete comparison with the oracle. At full size the oracle recomputes
+sampled cells one by one; the evolution is checked through properties that
+hold at any size (norm of every realization, step sizes within the rule)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import philox
+from oracle import twa_oracle as tw
+from paper_2310_07119_amd import Plan, Problem, inputs
+from tests.gpu_util import TOL, oracle_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(name, precision, **over):
+    w = dict(inputs.WORKLOADS[name])
+    w.update(over)
+    return Problem(n=w["n"], box=w["box"], hbar_m=w["hbar_m"], G=w["G"], m_tot=w["m_tot"], n_tot=w["n_tot"],
+                   n_real=w["n_real"], precision=precision), w
+
+
+def test_kgauss_512cube_fp32():
+    p, w = _problem("3d_n512_kgauss", "fp32", n_real=8)
+    print("512^3 momentum-space Gaussian, 8 realizations, fp32", flush=True)
+    psi_cl = inputs.initial_field("3d_n512_kgauss")
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    seed = 31
+    psi = plan.sample(cl, seed)
+    torch.cuda.synchronize()
+    # sampled cells recomputed by the oracle's generator, one by one
+    rng = np.random.default_rng(0)
+    g = rng.integers(0, p.ncell, 64).astype(np.uint64)
+    r = rng.integers(0, p.n_real, 64).astype(np.uint64)
+    words = philox.philox4x64([g, r, np.zeros_like(g), np.zeros_like(g)], (seed, tw.SAMPLE_KEY_TAG))
+    z1, z2 = philox.box_muller(words[0], words[1])
+    grid = tw.Grid(p.n, p.box)
+    sc = tw.noise_scale(grid, p.n_tot)
+    flat_cl = psi_cl.reshape(-1)
+    expect = (flat_cl.real[g.astype(np.int64)] + z1 * sc) + 1j * (flat_cl.imag[g.astype(np.int64)] + z2 * sc)
+    got = psi.reshape(p.n_real, -1)[torch.from_numpy(r.astype(np.int64)).cuda(),
+                                     torch.from_numpy(g.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.array_equal(got, expect.astype(np.complex64))
+    n0 = plan.moments(psi, energy=False, per_cell=False)["norm"].cpu().numpy()
+    clt = cl.to(torch.complex64).clone()
+    dts = plan.step_adaptive(psi, 3, w["dt"], courant=0.5, psi_classical=clt).cpu().numpy()
+    n1 = plan.moments(psi, energy=False, per_cell=False)["norm"].cpu().numpy()
+    assert np.all(np.abs(n1 / n0 - 1.0) < 1e-5)
+    kin = tw.kinetic_dt_bound(tw.Problem(grid, p.hbar_m, p.G, p.m_tot))
+    assert np.all(dts > 0) and np.all(dts <= w["dt"]) and np.all(dts <= 0.5 * kin * (1 + 1e-12))
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
+
+
+def test_kgauss_32cube_subset_vs_oracle():
+    """The same problem family regenerated at 32^3, FP32 split with adaptive
+    steps, against the oracle's adaptive evolution (every realization)."""
+    p, w = _problem("3d_n512_kgauss", "fp32", n=(32, 32, 32), n_real=6, n_tot=1e3 * 32 ** 3)
+    psi_cl = inputs.initial_field("3d_n512_kgauss", n=(32, 32, 32))
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 3)
+    clt = cl.to(torch.complex64).clone()
+    psi0 = psi.cpu().numpy().astype(np.complex128)
+    nsteps = 12
+    dts = plan.step_adaptive(psi, nsteps, w["dt"], courant=0.5, psi_classical=clt).cpu().numpy()
+    prob = oracle_problem(p)
+    cl0 = psi_cl.astype(np.complex64).astype(np.complex128)
+    ref, rdts = tw.evolve_adaptive(prob, np.concatenate([psi0, cl0[None]]), nsteps, w["dt"], 0.5)
+    assert rel(dts, rdts) < 1e-6
+    assert rel(psi.cpu().numpy(), ref[:p.n_real]) < TOL["fp32"]
+    assert rel(clt.cpu().numpy(), ref[p.n_real]) < TOL["fp32"]
+    plan.close()

@@ -63,7 +63,7 @@ def test_2d_workload_full_size_sampled(precision):
     psi = plan.sample(cl, seed)
     clt = cl.to(p.cdtype).clone()
     plan.step(psi, nsteps, w["dt"], clt)
-    m = plan.moments(psi, clt, modes=True)
+    m = plan.moments(psi, clt, modes=True, decoherence=True)
     host = psi.cpu().numpy()
     prob = oracle_problem(p)
     tol = TOL[precision]
@@ -73,12 +73,13 @@ def test_2d_workload_full_size_sampled(precision):
             x0 = x0.astype(np.complex64).astype(np.complex128)
         ref = tw.evolve(prob, x0, nsteps, w["dt"])[0]
         assert rel(host[r], ref) < tol, r
-    om = tw.moments(prob, host.astype(np.complex128), p.n_tot, clt.cpu().numpy().astype(np.complex128), modes=True)
-    for k in ("mean_psi", "mean_rho", "var_rho", "norm"):
+    om = tw.moments(prob, host.astype(np.complex128), p.n_tot, clt.cpu().numpy().astype(np.complex128), modes=True,
+                    decoherence_=True)
+    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "var_amp", "var_phase"):
         assert rel(m[k].cpu().numpy(), om[k]) < 1e-12, k
     # mode occupations: the GPU transforms in the plan's precision
     assert rel(m["mode_occ"].cpu().numpy(), om["mode_occ"]) < (1e-12 if precision == "fp64" else 1e-5)
-    for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2"):
+    for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2", "Var_A", "Var_phi"):
         assert abs(m[k] - om[k]) < 1e-11 * abs(om[k]), k
     del psi, host
     plan.close()

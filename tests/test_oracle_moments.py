@@ -144,3 +144,53 @@ def test_mode_occupation_half_quantum_at_t0():
     occ_cl = np.abs(tw.mode_amplitudes(prob, psi_cl, n_tot)) ** 2
     sigma = np.sqrt((2 * occ_cl + 0.5) * 0.5 / ns)
     assert np.all(np.abs(m["mode_occ"] - occ_cl - 0.5) < 6 * sigma)
+
+
+def test_decoherence_brute_force_tiny():
+    """Amplitude/phase spread summed by hand on 3 realizations of 6 cells,
+    including a phase deviation beyond pi/2 and the normal-ordering shift."""
+    grid = tw.Grid((6,), (1.5,))
+    prob = tw.Problem(grid)
+    rng = np.random.default_rng(8)
+    psi = rng.standard_normal((3, 6)) + 1j * rng.standard_normal((3, 6))
+    n_tot = 4.0
+    va, vp, VA, VP = tw.decoherence(prob, psi, n_tot)
+    dV = 0.25
+    ta = tp = 0.0
+    import cmath
+    import math
+    for g in range(6):
+        vals = [complex(psi[r, g]) for r in range(3)]
+        m1 = sum(vals) / 3
+        amps = [abs(v) for v in vals]
+        ma = sum(amps) / 3
+        a_var = sum((x - ma) ** 2 for x in amps) / 3
+        dev = [cmath.phase(v / m1) for v in vals]       # same angle as v conj(m1)
+        p_var = sum(d * d for d in dev) / 3
+        assert abs(va[g] - a_var) < 1e-13 and abs(vp[g] - p_var) < 1e-13
+        occ = sum(abs(v) ** 2 for v in vals) / 3 - 1 / (2 * n_tot * dV)
+        ta += dV * occ * a_var / ma
+        tp += dV * occ * p_var / (math.pi / math.sqrt(3))
+    assert abs(VA - ta) < 1e-13 and abs(VP - tp) < 1e-13
+
+
+def test_decoherence_limits():
+    """A coherent ensemble (identical realizations) has no spread at all; with
+    uniformly random phases at fixed amplitude the amplitude spread vanishes
+    and <dphi^2> tends to pi^2/3, the variance of a uniform angle."""
+    grid = tw.Grid((16,), (1.0,))
+    prob = tw.Problem(grid)
+    base = inputs.lognormal_field((16,), (1.0,), seed=1)
+    same = np.repeat(base[None], 5, axis=0)
+    va, vp, VA, VP = tw.decoherence(prob, same, 1e30)
+    assert np.all(va < 1e-28) and np.all(vp == 0.0) and abs(VA) < 1e-25 and VP == 0.0
+    rng = np.random.default_rng(2)
+    ns = 20000
+    phases = rng.uniform(-np.pi, np.pi, (ns, 16))
+    psi = np.abs(base)[None] * np.exp(1j * phases)
+    va, vp, VA, VP = tw.decoherence(prob, psi, 1e30)
+    assert np.all(va < 1e-20)   # rounding only: amplitudes are equal
+    # the deviation is taken from the (nearly random) phase of the mean field: still uniform on the circle
+    assert np.all(np.abs(vp - np.pi ** 2 / 3) < 0.1)
+    norm = (np.abs(base) ** 2).sum() * grid.dV
+    assert abs(VP - norm * (np.pi ** 2 / 3) / (np.pi / np.sqrt(3))) < 0.05 * VP
