@@ -14,6 +14,7 @@ Extra objects in the line:
   fp32_split    the FP32-split form on the same workload, with its normwise error
                 against the FP64 run for each per-cell moment
   adaptive      the same workload with step sizes chosen on the device
+  tracers       the same workload with test particles in every field
   batched       the three-size 3D soliton ensemble advanced from one HIP graph
   surrogate     the reduced FNO surrogate study
 """
@@ -157,6 +158,43 @@ def run_adaptive(wl, precision, steps, warmup, seed=20231007, courant=0.5):
             "simulated_time": float(d.sum()), "timed": "tw_step_adaptive only (no sampling or moments)"}
 
 
+def run_tracers(wl, precision, steps, warmup, ntracer=64, seed=20231007):
+    """The same workload with ntracer test particles per field pushed in every
+    field's own potential (tw_step_tracers); reports the step time and the
+    particles' spread over the realizations at the end."""
+    import numpy as np
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision=precision)
+    plan = Plan(p)
+    plan.autotune()
+    cl = torch.from_numpy(inputs.initial_field(wl["name"])).cuda()
+    psi = plan.sample(cl, seed)
+    clt = cl.to(p.cdtype).clone()
+    D = len(p.n)
+    rng = np.random.default_rng(seed)
+    tr0 = np.zeros((p.n_real + 1, ntracer, 2 * D))
+    tr0[:, :, :D] = rng.uniform(0.0, 1.0, (1, ntracer, D)) * np.array(p.box)   # same start in every field
+    tr = torch.from_numpy(tr0).cuda()
+    if warmup > 0:
+        plan.step_tracers(psi, warmup, wl["dt"], tr, clt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step_tracers(psi, steps, wl["dt"], tr, clt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    spread = plan.tracer_spread(tr).cpu().numpy()
+    plan.close()
+    del psi, clt, tr
+    torch.cuda.empty_cache()
+    prod = np.sqrt(spread[:, :D] * spread[:, D:])
+    return {"value": p.n_real * p.ncell * steps / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
+            "tracers_per_field": ntracer, "median_dx_dp": float(np.median(prod)),
+            "timed": "tw_step_tracers only"}
+
+
 def run_batched(steps, warmup, seed=7):
     """The three-size 3D soliton ensemble (FP32 split) advanced as one batch:
     every pass is one grouped launch over all classes and the K steps are one
@@ -248,6 +286,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-tracers", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -296,6 +335,10 @@ def main():
         ad["speedup_per_simulated_time"] = (ad["simulated_time"] / (args.steps * ad["ms_per_step"])) / (
             wl["dt"] / main_run["ms_per_step"])
         log(f"adaptive: {out['adaptive']}")
+    if not args.no_tracers:
+        out["tracers"] = run_tracers(wl, args.precision, args.steps, args.warmup)
+        out["tracers"]["fixed_step_ms_per_step"] = main_run["ms_per_step"]
+        log(f"tracers: {out['tracers']}")
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)
         log(f"batched: {out['batched']}")

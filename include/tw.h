@@ -130,6 +130,28 @@ int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double
 int tw_step_adaptive(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt_max,
                      double courant, double* dt_out, void* stream);
 
+/* tw_step with test particles (Sec. "Modeling decoherence"): every field
+ * carries ntracer particles that move in that field's own potential,
+ * dr/dt = v, dv/dt = -grad V(r), advanced in the same splitting as the field:
+ * r += v dt/2; v -= dt grad V(r) with the potential of the field's kick;
+ * r += v dt/2. grad V is the fourth-order central difference on the grid
+ * interpolated linearly (cloud-in-cell) to the particle. Positions are kept
+ * unwrapped (the periodic box is used only to locate the cell).
+ *   tracers : device, [nfield][ntracer][2 D] doubles, nfield = n_real (+1 with
+ *             psi_classical, whose particles come last): r_0..r_{D-1},
+ *             v_0..v_{D-1}; updated in place. 8-byte aligned.
+ * D >= 2 only. Other arguments as tw_step. */
+int tw_step_tracers(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt,
+                    double* tracers, int64_t ntracer, void* stream);
+
+/* Spread of the test particles over the realizations (the first n_real
+ * entries of `tracers`): out[i][k] = plug-in variance of coordinate k of
+ * particle i (k < D positions, then D velocities); the per-axis uncertainty
+ * product is sqrt(out[i][d] * out[i][D + d]).
+ *   tracers : device, [>= n_real][ntracer][2 D] doubles.
+ *   out     : device, [ntracer][2 D] doubles. */
+int tw_tracer_spread(tw_plan plan, const double* tracers, int64_t ntracer, double* out, void* stream);
+
 /* Outputs of tw_moments. Every pointer is a caller-owned device array and may
  * be NULL to skip that output. */
 typedef struct {

@@ -254,6 +254,86 @@ def evolve_adaptive(prob, psi, nsteps, dt_max, courant):
     return psi, np.array(dts[: int(nsteps)])
 
 
+# ---------------------------------------------------------- tracer particles
+def grid_gradient(prob, V):
+    """Gradient of V on the grid by fourth-order central differences along
+    each axis: (-V[g+2] + 8 V[g+1] - 8 V[g-1] + V[g-2]) / (12 dx), periodic.
+    V carries a leading field axis; returns one array per spatial axis (x first)."""
+    g = prob.grid
+    out = []
+    for d in range(g.dim):
+        ax = V.ndim - 1 - d
+        dx = g.box[d] / g.n[d]
+        f = lambda s: np.roll(V, -s, axis=ax)
+        out.append((-f(2) + 8.0 * f(1) - 8.0 * f(-1) + f(-2)) / (12.0 * dx))
+    return out
+
+
+def interpolate(prob, F, pos):
+    """Linear (cloud-in-cell) interpolation of the grid field F (leading
+    field axis) at positions pos[f][i][d] (any real coordinates: wrapped into
+    the periodic box). Returns [field][particle]."""
+    g = prob.grid
+    nf, npart = pos.shape[0], pos.shape[1]
+    out = np.zeros((nf, npart))
+    for f in range(nf):
+        flat = F[f].reshape(-1)
+        for i in range(npart):
+            base = []
+            frac = []
+            for d in range(g.dim):
+                s = (pos[f, i, d] % g.box[d]) / (g.box[d] / g.n[d])
+                i0 = int(np.floor(s))
+                base.append(i0)
+                frac.append(s - i0)
+            acc = 0.0
+            for corner in range(1 << g.dim):
+                w = 1.0
+                idx = 0
+                stride = 1
+                for d in range(g.dim):
+                    bit = (corner >> d) & 1
+                    w *= frac[d] if bit else 1.0 - frac[d]
+                    idx += ((base[d] + bit) % g.n[d]) * stride
+                    stride *= g.n[d]
+                acc += w * flat[idx]
+            out[f, i] = acc
+    return out
+
+
+def step_tracers(prob, psi, tracers, dt):
+    """One step of fields and test particles (Sec. "Modeling decoherence":
+    each realization's particles move in that realization's own potential,
+    dr/dt = v, dv/dt = -grad V_s(r)). The particles follow the same splitting
+    as the fields: half drift r += v dt/2, kick v -= dt grad V(r) with the
+    potential the field kick uses, half drift. tracers[f][i] = (r_0..r_{D-1},
+    v_0..v_{D-1}); positions are not wrapped (spreads need unwrapped paths)."""
+    D = prob.grid.dim
+    psi = drift(prob, psi, dt / 2.0)
+    V = potential(prob, density(prob, psi))
+    tr = tracers.copy()
+    tr[:, :, :D] += 0.5 * dt * tr[:, :, D:]
+    grads = grid_gradient(prob, V)
+    for d in range(D):
+        tr[:, :, D + d] -= dt * interpolate(prob, grads[d], tr[:, :, :D])
+    tr[:, :, :D] += 0.5 * dt * tr[:, :, D:]
+    psi = kick(prob, psi, V, dt)
+    return drift(prob, psi, dt / 2.0), tr
+
+
+def evolve_tracers(prob, psi, tracers, nsteps, dt):
+    for _ in range(int(nsteps)):
+        psi, tracers = step_tracers(prob, psi, tracers, dt)
+    return psi, tracers
+
+
+def tracer_spread(tracers, n_real):
+    """Plug-in variances over the realizations (the first n_real entries) of
+    every particle's position and velocity components: [particle][2D]."""
+    t = tracers[:n_real]
+    return ((t - t.mean(axis=0)[None]) ** 2).mean(axis=0)
+
+
 # ------------------------------------------------------------- diagnostics
 def norm(prob, psi):
     """sum_g |psi'_g|^2 dV per realization (1 for a normalised field)."""

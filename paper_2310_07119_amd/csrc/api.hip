@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -185,6 +186,12 @@ struct Adapt {
   double* dt_out;
 };
 
+// Test particles advanced with the fields (tw_step_tracers).
+struct Tracers {
+  double* tr;
+  int64_t ntracer;
+};
+
 // Kinetic bound on the step (footnote on the time step of Sec. "Numerical
 // implementation"): the phase gradient must not alias, dt < 4 pi /
 // (hbar k_max dk) with k_max = pi/dx and dk = 2 pi/L, per axis.
@@ -201,7 +208,7 @@ double kinetic_dt_bound(const Plan& P) {
 // already validated). With `ad`, the kick factor and the drift tables of every
 // step come from device memory, written by launch_adapt after each kick pass.
 int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hipStream_t s,
-                 const Adapt* ad = nullptr) {
+                 const Adapt* ad = nullptr, const Tracers* tc = nullptr) {
   const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
   const double h = 0.5 * dt;
   // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
@@ -255,11 +262,18 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
       return launch_adapt(P, -1, nsteps == 1, ad->dt_max, ad->courant, ad->dtk, ad->dt_out, s);
     }));
   }
-  // kick pass of step st: the kick factor and max |V| slot of the adaptive state
+  // kick pass of step st: the kick factor and max |V| slot of the adaptive
+  // state; with test particles it also leaves the potentials in the scratch
   auto kick_args = [&](PassArgs& b, int64_t st) {
+    if (tc) b.store_v = 1;
     if (!ad) return;
     b.kick_dev = P.adapt + 6 + st % 2;
     b.vmax = P.adapt + kAdaptScalars + (st % 3) * kVmaxBuckets;
+  };
+  // particles of every field after the kick pass whose storage order is perm
+  auto push = [&](const int (&perm)[3]) -> hipError_t {
+    if (!tc) return hipSuccess;
+    return timed(P, KIND_MODES, s, [&] { return launch_tracers(P, tc->tr, nfield, tc->ntracer, perm, dt, s); });
   };
   auto after_kick = [&](int64_t st) -> hipError_t {
     if (!ad) return hipSuccess;
@@ -314,6 +328,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
         TW_HIP(go(PASS_ZPOISSON, o0, o1, nullptr, 0));
         // kick and drift along o0; fields move to the other buffer, o1-contiguous
         TW_HIP(go(PASS_KICK_DRIFT, o0, o0, ph_step(o0, st, last), 1, st));
+        TW_HIP(push({o0, o1, 2}));
         TW_HIP(after_kick(st));
         if (!last) {
           TW_HIP(go(PASS_DRIFT_RHO, o1, o1, ph_step(o1, st, false), 0));
@@ -348,6 +363,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
         kick_args(b, st);
         TW_HIP(pass(P, b, PASS_KICK_DRIFT, o[0], ph_step(o[0], st, last), s, c0, nc));
       }
+      TW_HIP(push({0, 1, 2}));
       TW_HIP(after_kick(st));
       if (!last) {
         for (int i = 1; i < D - 1; ++i) TW_HIP(run(PASS_DRIFT, o[i], ph_step(o[i], st, false)));
@@ -560,6 +576,32 @@ int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, vo
   if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
   if (nsteps == 0) return TW_OK;
   return enqueue_step(P, psi, psi_cl, nsteps, dt, reinterpret_cast<hipStream_t>(stream));
+}
+
+int tw_step_tracers(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, double* tracers,
+                    int64_t ntracer, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (int rc = check_ptr(P, psi, "psi", false)) return rc;
+  if (int rc = check_ptr(P, psi_cl, "psi_classical", true)) return rc;
+  if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
+  if (!tracers || ntracer < 1) return fail(TW_EINVAL, "tracers must be a device array with ntracer >= 1");
+  if (reinterpret_cast<uintptr_t>(tracers) % 8 != 0) return fail(TW_ELAYOUT, "tracers must be 8-byte aligned");
+  if (P.dim < 2 || !P.z) return fail(TW_EUNSUPPORTED, "test particles need D >= 2 (all axes >= 16 points)");
+  if (P.chunk_pairs > 0 && P.chunk_pairs < P.npairs)
+    return fail(TW_EUNSUPPORTED, "test particles need the whole ensemble in one chunk (TW_CHUNK_PAIRS)");
+  if (nsteps == 0) return TW_OK;
+  Tracers tc{tracers, ntracer};
+  return enqueue_step(P, psi, psi_cl, nsteps, dt, reinterpret_cast<hipStream_t>(stream), nullptr, &tc);
+}
+
+int tw_tracer_spread(tw_plan plan, const double* tracers, int64_t ntracer, double* out, void* stream) {
+  if (!plan) return fail(TW_EINVAL, "NULL plan");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (!tracers || !out || ntracer < 1) return fail(TW_EINVAL, "bad tracer spread arguments");
+  TW_HIP(launch_tracer_spread(P, tracers, ntracer, out, reinterpret_cast<hipStream_t>(stream)));
+  return TW_OK;
 }
 
 int tw_step_adaptive(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt_max, double courant,

@@ -38,6 +38,7 @@ struct PassArgs {
   void* psi_cl_t;          // ... its classical-field slot
   const double* kick_dev;  // PASS_KICK_DRIFT: kick factor dt/hbar read from device memory (overrides kick)
   double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V|, kVmaxBuckets slots (atomic max on the bits)
+  int32_t store_v;         // PASS_KICK_DRIFT: write the real-space potentials V_A + i V_B back into the pair scratch
 };
 
 enum PassMode : int {
@@ -113,6 +114,12 @@ hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hi
 hipError_t launch_adapt(const Plan& P, int64_t step, int last_next, double dt_max, double courant, double dtk,
                         double* dt_out, hipStream_t s);
 hipError_t launch_adapt_clear(const Plan& P, hipStream_t s);
+// Test particles: one leapfrog step of every field's particles in the
+// potential the kick pass left in the pair scratch (stored with physical axis
+// perm[0] fastest, then perm[1], perm[2]).
+hipError_t launch_tracers(const Plan& P, double* tr, int64_t nfield, int64_t ntracer, const int perm[3], double dt,
+                          hipStream_t s);
+hipError_t launch_tracer_spread(const Plan& P, const double* tr, int64_t ntracer, double* out, hipStream_t s);
 hipError_t launch_field_mean(const Plan& P, const void* psi, const void* psi_cl, int64_t nfield,
                              double* out_mean, hipStream_t s);
 hipError_t launch_sample(const Plan& P, const void* psi_cl, uint64_t seed, int64_t real_offset,

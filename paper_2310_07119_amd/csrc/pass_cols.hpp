@@ -227,6 +227,12 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
       mx = block_max(mx, red);
       if (tid == 0) record_max(a.vmax + ((bx + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
+    if (a.store_v) {  // the potentials, for the test particles
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) pencil_put(q, V[q]);
+      lds_barrier();
+      tile_store(zp);
+    }
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
     for (int k = 0; k < 2; ++k) {
       const int64_t f = k == 0 ? fA : fB;

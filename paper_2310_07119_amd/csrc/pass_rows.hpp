@@ -169,6 +169,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       mx = block_max(mx, red);
       if (tid == 0) record_max(a.vmax + ((bx + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
+    if (a.store_v) store(zp, zv);  // the potentials, for the test particles
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
 #pragma unroll
     for (int m = 0; m < R; ++m) {

@@ -23,7 +23,8 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
                 "nonfinite", "energy_classical")
 
 # Exported entry points and their argument types (mirrors include/tw.h).
-EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_step_adaptive", "tw_moments",
+EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_step_adaptive", "tw_step_tracers",
+           "tw_tracer_spread", "tw_moments",
            "tw_plan_autotune", "tw_batch_create", "tw_batch_plan", "tw_batch_autotune", "tw_batch_step",
            "tw_batch_destroy", "tw_fno_param_count", "tw_fno_create", "tw_fno_destroy", "tw_fno_init_params",
            "tw_fno_forward", "tw_fno_backward", "tw_fno_mse", "tw_fno_adam", "tw_fno_last_error",
@@ -68,6 +69,8 @@ def load_library(path=LIB_PATH):
     lib.tw_sample.argtypes = [vp, vp, u64, i64, vp, vp]
     lib.tw_step.argtypes = [vp, vp, vp, i64, dbl, vp]
     lib.tw_step_adaptive.argtypes = [vp, vp, vp, i64, dbl, dbl, vp, vp]
+    lib.tw_step_tracers.argtypes = [vp, vp, vp, i64, dbl, vp, i64, vp]
+    lib.tw_tracer_spread.argtypes = [vp, vp, i64, vp, vp]
     lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
     lib.tw_plan_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.tw_batch_create.argtypes = [ctypes.POINTER(TwProblem), ctypes.c_int32, ctypes.POINTER(vp)]
@@ -224,6 +227,27 @@ class Plan:
         _check(self._lib.tw_step(self.handle, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt), _stream()),
                "tw_step")
         return psi
+
+    def step_tracers(self, psi, nsteps, dt, tracers, psi_classical=None):
+        """tw_step with test particles: tracers is a float64 device tensor
+        [nfield][ntracer][2 D] (positions, then velocities), updated in place."""
+        assert psi.dtype == self.problem.cdtype and psi.is_contiguous()
+        if psi_classical is not None:
+            assert psi_classical.dtype == self.problem.cdtype and psi_classical.is_contiguous()
+        nfield = self.problem.n_real + (1 if psi_classical is not None else 0)
+        assert tracers.dtype == torch.float64 and tracers.is_contiguous()
+        assert tracers.dim() == 3 and tracers.shape[0] == nfield and tracers.shape[2] == 2 * len(self.problem.n)
+        _check(self._lib.tw_step_tracers(self.handle, _ptr(psi), _ptr(psi_classical), int(nsteps), float(dt),
+                                         _ptr(tracers), int(tracers.shape[1]), _stream()), "tw_step_tracers")
+        return tracers
+
+    def tracer_spread(self, tracers):
+        """Variances over the realizations of every particle coordinate [ntracer][2 D] (tw_tracer_spread)."""
+        assert tracers.dtype == torch.float64 and tracers.is_contiguous()
+        out = torch.empty((tracers.shape[1], tracers.shape[2]), dtype=torch.float64, device=tracers.device)
+        _check(self._lib.tw_tracer_spread(self.handle, _ptr(tracers), int(tracers.shape[1]), _ptr(out), _stream()),
+               "tw_tracer_spread")
+        return out
 
     def step_adaptive(self, psi, nsteps, dt_max, courant=1.0, psi_classical=None):
         """Advance psi (and psi_classical) in place by nsteps steps whose sizes the

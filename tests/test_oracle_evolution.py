@@ -247,3 +247,41 @@ def test_adaptive_lag_rule():
         V = tw.potential(prob, tw.density(prob, half))
         assert dts[n + 2] == min(1.0, 0.5 * tw.kinetic_dt_bound(prob), 0.5 * 2 * np.pi * 0.05 / np.abs(V).max())
         psi = tw.step(prob, psi, dts[n])
+
+
+# ----------------------------------------------------------- tracer particles
+def test_tracers_move_straight_without_gravity():
+    grid = tw.Grid((16, 8), (1.0, 0.5))
+    prob = tw.Problem(grid, G=0.0)
+    psi = inputs.lognormal_field((16, 8), (1.0, 0.5), seed=2)[None]
+    tr = np.array([[[0.1, 0.2, 3.0, -1.5], [0.9, 0.45, -0.2, 0.7]]])
+    _, got = tw.evolve_tracers(prob, psi, tr, 5, 1e-2)
+    expect = tr.copy()
+    expect[:, :, :2] += 5 * 1e-2 * tr[:, :, 2:]
+    assert np.allclose(got, expect, rtol=0, atol=1e-15)
+
+
+def test_fourth_order_gradient_of_a_cosine():
+    """The fourth-order difference of cos(kx) is -sin(kx) (8 sin(k dx) - sin(2 k dx)) / (6 dx)."""
+    n, L = 32, 2.0
+    grid = tw.Grid((n,), (L,))
+    prob = tw.Problem(grid)
+    x = np.arange(n) * L / n
+    k, dx = 2 * np.pi * 3 / L, L / n
+    (gx,) = tw.grid_gradient(prob, np.cos(k * x)[None])
+    expect = -np.sin(k * x) * (8 * np.sin(k * dx) - np.sin(2 * k * dx)) / (6 * dx)
+    assert np.allclose(gx[0], expect, rtol=0, atol=1e-13)
+    assert np.max(np.abs(gx[0] + k * np.sin(k * x))) < 1e-2 * k   # and it approximates the derivative
+
+
+def test_cic_interpolation_is_exact_for_linear_fields():
+    """Between grid points a bilinear field is reproduced exactly (away from the
+    periodic seam), and positions outside the box wrap."""
+    grid = tw.Grid((8, 4), (2.0, 1.0))
+    prob = tw.Problem(grid)
+    y, x = np.meshgrid(np.arange(4) * 0.25, np.arange(8) * 0.25, indexing="ij")
+    F = (1.0 + 2.0 * x - 3.0 * y + 0.5 * x * y)[None]
+    pos = np.array([[[0.3, 0.1], [1.6, 0.7], [0.3 + 2.0, 0.1 - 1.0]]])
+    got = tw.interpolate(prob, F, pos)
+    for i, (px, py) in enumerate([(0.3, 0.1), (1.6, 0.7), (0.3, 0.1)]):
+        assert abs(got[0, i] - (1.0 + 2.0 * px - 3.0 * py + 0.5 * px * py)) < 1e-14
