@@ -15,6 +15,8 @@ Extra objects in the line:
                 against the FP64 run for each per-cell moment
   adaptive      the same workload with step sizes chosen on the device
   tracers       the same workload with test particles in every field
+  diagnostics   tw_moments with every optional output
+  scale_512cube the paper's momentum-space Gaussian problem at 512^3 (FP32)
   batched       the three-size 3D soliton ensemble advanced from one HIP graph
   surrogate     the reduced FNO surrogate study
 """
@@ -195,6 +197,68 @@ def run_tracers(wl, precision, steps, warmup, ntracer=64, seed=20231007):
             "timed": "tw_step_tracers only"}
 
 
+def run_diagnostics(wl, precision, seed=20231007, reps=3):
+    """tw_moments with every optional output (energies, per-mode occupations,
+    amplitude and phase spread) on the sampled workload ensemble."""
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision=precision)
+    plan = Plan(p)
+    plan.autotune()
+    cl = torch.from_numpy(inputs.initial_field(wl["name"])).cuda()
+    psi = plan.sample(cl, seed)
+    clt = cl.to(p.cdtype).clone()
+    plan.moments(psi, clt, energy=True, modes=True, decoherence=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m = plan.moments(psi, clt, energy=True, modes=True, decoherence=True)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
+    return {"ms_per_call": 1e3 * el, "Q_raw": m["Q_raw"], "Var_A": m["Var_A"], "Var_phi": m["Var_phi"],
+            "timed": "tw_moments with energies, mode occupations and amplitude/phase spread"}
+
+
+def run_scale(steps, seed=5):
+    """The paper's momentum-space Gaussian test problem at 512^3 (FP32 split,
+    32 realizations + classical field, about 50 GiB of HBM): sampling, steps
+    with device-chosen sizes, moments."""
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    wl = dict(inputs.WORKLOADS["3d_n512_kgauss"])
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision="fp32")
+    t_ic = time.perf_counter()
+    cl = torch.from_numpy(inputs.initial_field("3d_n512_kgauss")).cuda()
+    t_ic = time.perf_counter() - t_ic
+    plan = Plan(p)
+    plan.autotune()
+    psi = plan.sample(cl, seed)
+    clt = cl.to(p.cdtype).clone()
+    plan.step_adaptive(psi, 1, wl["dt"], 0.5, clt)      # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dts = plan.step_adaptive(psi, steps, wl["dt"], 0.5, clt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m = plan.moments(psi, clt, energy=True)
+    free, total = torch.cuda.mem_get_info()
+    out = {"workload": "3d_n512_kgauss", "grid": list(p.n), "n_real": p.n_real, "precision": "fp32",
+           "value": p.n_real * p.ncell * steps / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
+           "dt_myr": float(dts[0]), "norm_mean": m["norm_mean"], "hbm_in_use_gib": round((total - free) / 2 ** 30, 1),
+           "host_ic_seconds": round(t_ic, 1)}
+    plan.close()
+    del psi, clt, cl
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(steps, warmup, seed=7):
     """The three-size 3D soliton ensemble (FP32 split) advanced as one batch:
     every pass is one grouped launch over all classes and the K steps are one
@@ -287,6 +351,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-tracers", action="store_true")
+    ap.add_argument("--no-diagnostics", action="store_true")
+    ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -339,6 +405,12 @@ def main():
         out["tracers"] = run_tracers(wl, args.precision, args.steps, args.warmup)
         out["tracers"]["fixed_step_ms_per_step"] = main_run["ms_per_step"]
         log(f"tracers: {out['tracers']}")
+    if not args.no_diagnostics:
+        out["diagnostics"] = run_diagnostics(wl, args.precision)
+        log(f"diagnostics: {out['diagnostics']}")
+    if not args.no_scale:
+        out["scale_512cube"] = run_scale(max(args.steps // 5, 2))
+        log(f"scale: {out['scale_512cube']}")
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)
         log(f"batched: {out['batched']}")

@@ -33,13 +33,9 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 
-# kernel kinds (as reported by tw_plan_get_profile) -> substrings of their
-# compiled names as rocprofv3 prints them
-KIND_PATTERNS = {
-    "pass_kick_drift": (", 5, true>", "cols_kernel<double, 512, 5>", "cols_kernel<float, 512, 5>",
-                        ", 5, false>"),
-    "pass_drift_rho": (", 1, true>", ", 1, false>", "cols_kernel<double, 512, 1>", "cols_kernel<float, 512, 1>"),
-}
+# kernel kinds (as reported by tw_plan_get_profile) -> pass mode in the
+# compiled kernel names (pass_kernel<T, N, MODE, ROWS> / cols_kernel<T, N, MODE>)
+KIND_MODES = {"pass_kick_drift": 5, "pass_drift_rho": 1, "pass_zpoisson": 3}
 SOURCES = ("csrc/fft.hpp", "csrc/common.hpp", "csrc/pass_common.hpp", "csrc/pass_rows.hpp", "csrc/pass_cols.hpp",
            "csrc/kernels_step.hip", "csrc/kernels_cols.hip")
 
@@ -77,9 +73,9 @@ def _per_dispatch(rows, counter, match):
 
 
 def summarize(a):
-    pats = KIND_PATTERNS[a.kind]
-    is_kind = lambda n: "pass_kernel" in n or "cols_kernel" in n
-    match = lambda n: is_kind(n) and any(p in n for p in pats)
+    ctype = "double" if a.precision == "fp64" else "float"
+    tag = f"<{ctype}, {a.length}, {KIND_MODES[a.kind]}"
+    match = lambda n: ("pass_kernel" in n or "cols_kernel" in n) and tag in n
     fetch = _per_dispatch(_rows(a.fetch), "FETCH_SIZE", match)
     write = _per_dispatch(_rows(a.write), "WRITE_SIZE", match)
     copy_match = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
@@ -200,6 +196,8 @@ def main():
     for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
         s.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     s.add_argument("--kind", default="pass_kick_drift")
+    s.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    s.add_argument("--length", type=int, default=512, help="transform length of the pass kernels")
     s.add_argument("--copy-mib", dest="copy_mib", type=int, default=1024)
     s.add_argument("--commands", default="")
     k = sub.add_parser("kernels")
