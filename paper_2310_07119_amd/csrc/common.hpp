@@ -56,17 +56,10 @@ __device__ __forceinline__ cx<T> mul_d(cx<T> a, double f) {
 // through r^9 and r^10), and the quadrant k mod 4 maps them to sin and cos of
 // arg. Arguments beyond 10^6 (never reached by kick phases) take the library
 // sincos.
-__device__ __forceinline__ bool quarter_turns(double arg, double& r, int& q) {
-  if (fabs(arg) <= 0.78539816339744830962) {  // already reduced (the common case: small kick phases)
-    r = arg;
-    q = 0;
-    return true;
-  }
-  if (!(fabs(arg) <= 1.0e6)) return false;
+__device__ __forceinline__ double quarter_turns(double arg, int& q) {
   const double k = rint(arg * 0.63661977236758134308);  // 2/pi
-  r = ((arg - k * 1.5707963267341256) - k * 6.077100506303966e-11) - k * 2.0222662487959506e-21;
   q = (int)((long long)k & 3);
-  return true;
+  return ((arg - k * 1.5707963267341256) - k * 6.077100506303966e-11) - k * 2.0222662487959506e-21;
 }
 
 // (cos, sin) of the reduced angle mapped to the quadrant: returns exp(-i arg).
@@ -82,60 +75,77 @@ __device__ __forceinline__ cx<T> quadrant(T c, T s, int q) {
   return {cosx, -sinx};
 }
 
-template <class T>
-__device__ __forceinline__ cx<T> expmi(double arg);
-template <>
-__device__ __forceinline__ cx<double> expmi<double>(double arg) {
-  double x;
-  int q;
-  if (quarter_turns(arg, x, q)) {
-    const double x2 = x * x;
-    double ps = -1.0 / 355687428096000.0;
-    ps = ps * x2 + 1.0 / 1307674368000.0;
-    ps = ps * x2 - 1.0 / 6227020800.0;
-    ps = ps * x2 + 1.0 / 39916800.0;
-    ps = ps * x2 - 1.0 / 362880.0;
-    ps = ps * x2 + 1.0 / 5040.0;
-    ps = ps * x2 - 1.0 / 120.0;
-    ps = ps * x2 + 1.0 / 6.0;
-    double pc = 1.0 / 20922789888000.0;
-    pc = pc * x2 - 1.0 / 87178291200.0;
-    pc = pc * x2 + 1.0 / 479001600.0;
-    pc = pc * x2 - 1.0 / 3628800.0;
-    pc = pc * x2 + 1.0 / 40320.0;
-    pc = pc * x2 - 1.0 / 720.0;
-    pc = pc * x2 + 1.0 / 24.0;
-    pc = pc * x2 - 0.5;
-    const double s = x - x * x2 * ps;
-    const double c = 1.0 + x2 * pc;
-    return quadrant<double>(c, s, q);
-  }
-  double s, c;
-  sincos(arg, &s, &c);
-  return {c, -s};
+__device__ __forceinline__ void sincos_series(double x, double& s, double& c) {
+  const double x2 = x * x;
+  double ps = -1.0 / 355687428096000.0;
+  ps = ps * x2 + 1.0 / 1307674368000.0;
+  ps = ps * x2 - 1.0 / 6227020800.0;
+  ps = ps * x2 + 1.0 / 39916800.0;
+  ps = ps * x2 - 1.0 / 362880.0;
+  ps = ps * x2 + 1.0 / 5040.0;
+  ps = ps * x2 - 1.0 / 120.0;
+  ps = ps * x2 + 1.0 / 6.0;
+  double pc = 1.0 / 20922789888000.0;
+  pc = pc * x2 - 1.0 / 87178291200.0;
+  pc = pc * x2 + 1.0 / 479001600.0;
+  pc = pc * x2 - 1.0 / 3628800.0;
+  pc = pc * x2 + 1.0 / 40320.0;
+  pc = pc * x2 - 1.0 / 720.0;
+  pc = pc * x2 + 1.0 / 24.0;
+  pc = pc * x2 - 0.5;
+  s = x - x * x2 * ps;
+  c = 1.0 + x2 * pc;
 }
-template <>
-__device__ __forceinline__ cx<float> expmi<float>(double arg) {
-  double xr;
-  int q;
-  if (quarter_turns(arg, xr, q)) {
-    const float x = (float)xr, x2 = x * x;
-    float ps = 1.f / 362880.f;
-    ps = ps * x2 - 1.f / 5040.f;
-    ps = ps * x2 + 1.f / 120.f;
-    ps = ps * x2 - 1.f / 6.f;
-    float pc = -1.f / 3628800.f;
-    pc = pc * x2 + 1.f / 40320.f;
-    pc = pc * x2 - 1.f / 720.f;
-    pc = pc * x2 + 1.f / 24.f;
-    pc = pc * x2 - 0.5f;
-    return quadrant<float>(1.f + x2 * pc, x + x * x2 * ps, q);
+
+__device__ __forceinline__ void sincos_series(float x, float& s, float& c) {
+  const float x2 = x * x;
+  float ps = 1.f / 362880.f;
+  ps = ps * x2 - 1.f / 5040.f;
+  ps = ps * x2 + 1.f / 120.f;
+  ps = ps * x2 - 1.f / 6.f;
+  float pc = -1.f / 3628800.f;
+  pc = pc * x2 + 1.f / 40320.f;
+  pc = pc * x2 - 1.f / 720.f;
+  pc = pc * x2 + 1.f / 24.f;
+  pc = pc * x2 - 0.5f;
+  s = x + x * x2 * ps;
+  c = 1.f + x2 * pc;
+}
+
+template <class T>
+__device__ __forceinline__ cx<T> expmi(double arg) {
+  T s, c;
+  if constexpr (sizeof(T) == 8) {
+    if (fabs(arg) <= 0.03125) {
+      // typical kick phases are far below pi/4: for |x| <= 2^-5 the series
+      // through x^7 / x^8 already leave a remainder below x^9/9! < 2^-64 |x|
+      const double x = arg, x2 = x * x;
+      const double ps = ((-1.0 / 5040.0) * x2 + 1.0 / 120.0) * x2 - 1.0 / 6.0;
+      const double pc = (((1.0 / 40320.0) * x2 - 1.0 / 720.0) * x2 + 1.0 / 24.0) * x2 - 0.5;
+      return {1.0 + x2 * pc, -(x + x * x2 * ps)};
+    }
   }
-  const double two_pi = 6.283185307179586476925286766559;
-  double r = arg - two_pi * rint(arg * (1.0 / two_pi));
-  float s, c;
-  sincosf((float)r, &s, &c);
-  return {c, -s};
+  if (fabs(arg) <= 0.78539816339744830962) {  // small kick phases
+    sincos_series((T)arg, s, c);
+    return {c, -s};
+  }
+  if (fabs(arg) <= 1.0e6) {
+    int q;
+    const double r = quarter_turns(arg, q);
+    sincos_series((T)r, s, c);
+    return quadrant<T>(c, s, q);
+  }
+  if constexpr (sizeof(T) == 8) {
+    double sd, cd;
+    sincos(arg, &sd, &cd);
+    return {(T)cd, (T)(-sd)};
+  } else {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r = arg - two_pi * rint(arg * (1.0 / two_pi));
+    float sf, cf;
+    sincosf((float)r, &sf, &cf);
+    return {cf, -sf};
+  }
 }
 
 }  // namespace tw
