@@ -83,6 +83,7 @@ struct Fno {
   float* dz;     // [P][proj]
   float* parts;  // split-K partials
   int64_t parts_len;
+  double* parts2;  // FP64 sub-totals of groups of 32 partials
   void* block;   // single allocation
 };
 
@@ -102,10 +103,13 @@ hipError_t gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, float alpha, con
 }
 
 // dW[M x N] = A^T B summed over P positions, A = [P][M] rows, B = [P][N] rows,
-// split over K (positions) into partials that are then summed (FP64).
+// split over K (positions) into partials that are then summed (FP64). The
+// weight matrices are one or two tiles, so the split supplies the parallelism:
+// chunks of 512 positions give ~1000 workgroups at 256^2 x 8 fields (chunks of
+// 8192 left three quarters of the chip idle and made these the slowest GEMMs).
 hipError_t weight_grad(Fno& F, hipStream_t s, int64_t P, int64_t M, int64_t N, const float* A, const float* B,
                        float* out) {
-  int64_t chunk = std::gcd(P, (int64_t)8192);
+  int64_t chunk = std::gcd(P, (int64_t)512);
   int64_t nsplit = P / chunk;
   while (nsplit * M * N > F.parts_len || nsplit > 65535) {  // coarser split if the partial buffer is short
     chunk *= 2;
@@ -114,7 +118,7 @@ hipError_t weight_grad(Fno& F, hipStream_t s, int64_t P, int64_t M, int64_t N, c
   }
   hipError_t e = gemm(s, M, N, chunk, 1.f, A, 1, M, B, N, 1, 0.f, F.parts, N, 1, nsplit, chunk * M, chunk * N, M * N);
   if (e != hipSuccess) return e;
-  return launch_sum_parts(F.parts, (int)nsplit, M * N, out, 0, s);
+  return launch_sum_parts(F.parts, (int)nsplit, M * N, out, 0, s, F.parts2);
 }
 
 // S(v) -> out, saving the y-transformed input (bsav) for the backward.
@@ -211,7 +215,7 @@ int tw_fno_create(const tw_fno_config* cfg, int32_t max_batch, tw_fno* out) {
   const int64_t H = c.H, W = c.W, C = c.width, mx = c.modes_x, K2 = 2LL * c.modes_y, Lyr = c.layers;
   const int64_t P = (int64_t)max_batch * H * W;
   const int64_t big = std::max<int64_t>(C, c.proj);
-  F->parts_len = 64 * big * big;
+  F->parts_len = 1024 * big * big;
   struct Piece {
     float** p;
     int64_t n;
@@ -224,7 +228,8 @@ int tw_fno_create(const tw_fno_config* cfg, int32_t max_batch, tw_fno* out) {
       {&F->d_re, max_batch * H * mx * C}, {&F->d_im, max_batch * H * mx * C},
       {&F->c_re, max_batch * K2 * mx * C}, {&F->c_im, max_batch * K2 * mx * C},
       {&F->bb_re, max_batch * K2 * mx * C}, {&F->bb_im, max_batch * K2 * mx * C},
-      {&F->dz, P * std::max<int64_t>(c.proj, c.c_out)}, {&F->parts, F->parts_len}};
+      {&F->dz, P * std::max<int64_t>(c.proj, c.c_out)}, {&F->parts, F->parts_len},
+      {reinterpret_cast<float**>(&F->parts2), F->parts_len / 8}};  // ceil(nsplit/32) M N doubles
   int64_t total = 0;
   for (auto& pc : pieces) total += (pc.n + 63) / 64 * 64;
   if (hipMalloc(&F->block, sizeof(float) * total) != hipSuccess) {
@@ -352,13 +357,13 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
   const int64_t bstride = (int64_t)F.max_batch * K2 * mx * C;
   // projection 2
   FNO_HIP(weight_grad(F, s, P, c.proj, c.c_out, F.h, dy, grads + L.q2_w));
-  FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, F.parts, F.parts_len, s));
+  FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, F.parts, F.parts_len, F.parts2, s));
   FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1));
   FNO_HIP(launch_gelu_back(F.dz, F.z1, F.dz, P * c.proj, s));
   // projection 1
   const float* vL = F.v + (int64_t)c.layers * PC;
   FNO_HIP(weight_grad(F, s, P, C, c.proj, vL, F.dz, grads + L.q1_w));
-  FNO_HIP(launch_colsum(F.dz, P, c.proj, grads + L.q1_b, 0, F.parts, F.parts_len, s));
+  FNO_HIP(launch_colsum(F.dz, P, c.proj, grads + L.q1_b, 0, F.parts, F.parts_len, F.parts2, s));
   float* dv = F.t1;
   float* du = F.t2;
   FNO_HIP(gemm(s, P, C, c.proj, 1.f, F.dz, c.proj, 1, params + L.q1_w, 1, c.proj, 0.f, dv, C, 1));
@@ -371,7 +376,7 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
       FNO_HIP(hipMemcpyAsync(du, dv, sizeof(float) * P * C, hipMemcpyDeviceToDevice, s));
     }
     FNO_HIP(weight_grad(F, s, P, C, C, vl, du, grads + L.W[l]));
-    FNO_HIP(launch_colsum(du, P, (int)C, grads + L.b[l], 0, F.parts, F.parts_len, s));
+    FNO_HIP(launch_colsum(du, P, (int)C, grads + L.b[l], 0, F.parts, F.parts_len, F.parts2, s));
     const float* br = F.bsav + (2 * l) * bstride;
     const float* bi = F.bsav + (2 * l + 1) * bstride;
     if (int rc = spectral_bwd(F, s, batch, du, br, bi, params + L.Rre[l], params + L.Rim[l], grads + L.Rre[l],
@@ -380,7 +385,7 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
     FNO_HIP(gemm(s, P, C, C, 1.f, du, C, 1, params + L.W[l], 1, C, 1.f, dv, C, 1));
   }
   FNO_HIP(weight_grad(F, s, P, c.c_in, C, x, dv, grads + L.lift_w));
-  FNO_HIP(launch_colsum(dv, P, (int)C, grads + L.lift_b, 0, F.parts, F.parts_len, s));
+  FNO_HIP(launch_colsum(dv, P, (int)C, grads + L.lift_b, 0, F.parts, F.parts_len, F.parts2, s));
   return TW_OK;
 }
 

@@ -23,8 +23,9 @@ hipError_t launch_bias_act(float* u, const float* s, const float* bias, float* v
                            hipStream_t st);
 hipError_t launch_gelu_back(const float* g, const float* z, float* d, int64_t n, hipStream_t st);
 hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, float* parts,
-                         int64_t parts_len, hipStream_t st);
-hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st);
+                         int64_t parts_len, double* tmp, hipStream_t st);
+hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st,
+                            double* tmp);  // tmp: [ceil(nparts/32)][n] FP64 sub-totals, or NULL
 hipError_t launch_modemix_fwd(const float* br, const float* bi, const float* Rr, const float* Ri, float* cr,
                               float* ci, int nb, int nmode, int C, hipStream_t st);
 hipError_t launch_modemix_bwd(const float* br, const float* bi, const float* dcr, const float* dci, const float* Rr,

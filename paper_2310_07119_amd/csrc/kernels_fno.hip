@@ -27,21 +27,28 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
   return (unsigned short)(r >> 16);
 }
 
-constexpr int GT = 64;        // output tile edge
 constexpr int GK = 32;        // K per stage (one MFMA)
 constexpr int GLD = GK + 8;   // LDS row pitch in bf16 (16-byte pad)
 
+// One workgroup of 4 wavefronts computes a TM x TN tile of C; each wavefront
+// owns a 32 x 32 sub-tile (2 x 2 MFMA blocks of 16 x 16). TM x TN is 64 x 64,
+// or 128 x 32 for the skinny products (N <= 32: the pointwise layers), where
+// a square tile would leave half of its wavefronts on zero columns.
+template <int TM, int TN>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __align__(16) unsigned short As[GT * GLD];  // [m][k]
-  __shared__ __align__(16) unsigned short Bs[GT * GLD];  // [n][k]  (B transposed)
+  static_assert(TM * TN == 4096 && TM % 32 == 0 && TN % 32 == 0, "four 32x32 wavefront tiles");
+  constexpr int WN = TN / 32;  // wavefronts along n
+  constexpr int EA = TM * GK / 256, EB = TN * GK / 256;  // staged elements per thread
+  __shared__ __align__(16) unsigned short As[TM * GLD];  // [m][k]
+  __shared__ __align__(16) unsigned short Bs[TN * GLD];  // [n][k]  (B transposed)
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int64_t b = blockIdx.z;
-  const int64_t m0 = (int64_t)blockIdx.y * GT, n0 = (int64_t)blockIdx.x * GT;
+  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
   const float* __restrict__ A = g.A + b * g.sAb;
   const float* __restrict__ B = g.B + b * g.sBb;
   float* __restrict__ C = g.C + b * g.sCb;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wm = (w / WN) * 32, wn = (w % WN) * 32;
 
   f32x4 acc[2][2];
 #pragma unroll
@@ -49,28 +56,41 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // staging maps: 2048 elements per tile, 8 per thread; the faster-moving
-  // index follows the operand's unit stride when it has one
+  // staging maps: the faster-moving index follows the operand's unit stride
+  // when it has one
   const bool a_k_fast = g.sAk == 1;
   const bool b_n_fast = g.sBn == 1;
   for (int64_t k0 = 0; k0 < g.K; k0 += GK) {
+    float va[EA], vb[EB];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < EA; ++e) {  // issue every load of the stage before converting
       const int idx = tid + 256 * e;
-      const int mm = a_k_fast ? idx / GK : idx % GT;
-      const int kk = a_k_fast ? idx % GK : idx / GT;
+      const int mm = a_k_fast ? idx / GK : idx % TM;
+      const int kk = a_k_fast ? idx % GK : idx / TM;
       const int64_t gm = m0 + mm, gk = k0 + kk;
-      const float v = (gm < g.M && gk < g.K) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
-      As[mm * GLD + kk] = f32_to_bf16_rne(v);
+      va[e] = (gm < g.M && gk < g.K) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < EB; ++e) {
       const int idx = tid + 256 * e;
-      const int nn = b_n_fast ? idx % GT : idx / GK;
-      const int kk = b_n_fast ? idx / GT : idx % GK;
+      const int nn = b_n_fast ? idx % TN : idx / GK;
+      const int kk = b_n_fast ? idx / TN : idx % GK;
       const int64_t gn = n0 + nn, gk = k0 + kk;
-      const float v = (gn < g.N && gk < g.K) ? B[gk * g.sBk + gn * g.sBn] : 0.f;
-      Bs[nn * GLD + kk] = f32_to_bf16_rne(v);
+      vb[e] = (gn < g.N && gk < g.K) ? B[gk * g.sBk + gn * g.sBn] : 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + 256 * e;
+      const int mm = a_k_fast ? idx / GK : idx % TM;
+      const int kk = a_k_fast ? idx % GK : idx / TM;
+      As[mm * GLD + kk] = f32_to_bf16_rne(va[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + 256 * e;
+      const int nn = b_n_fast ? idx % TN : idx / GK;
+      const int kk = b_n_fast ? idx / TN : idx % GK;
+      Bs[nn * GLD + kk] = f32_to_bf16_rne(vb[e]);
     }
     __syncthreads();
     const int r = lane & 15, kq = (lane >> 4) * 8;
@@ -105,8 +125,13 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.batch > 65535) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((g.N + GT - 1) / GT), (unsigned)((g.M + GT - 1) / GT), (unsigned)g.batch);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+  if (g.N <= 32) {
+    dim3 grid((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 127) / 128), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_bf16_kernel<128, 32>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_bf16_kernel<64, 64>), grid, dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 
@@ -177,7 +202,7 @@ __global__ void __launch_bounds__(256) colsum_parts_kernel(const float* __restri
 }
 
 hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, float* parts,
-                         int64_t parts_len, hipStream_t st) {
+                         int64_t parts_len, double* tmp, hipStream_t st) {
   if (P <= 0 || C <= 0) return hipErrorInvalidValue;
   int TC = 1;
   while (TC * 2 <= C && TC * 2 <= 64) TC *= 2;
@@ -189,7 +214,7 @@ hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accum
   hipLaunchKernelGGL(colsum_parts_kernel, dim3((unsigned)nblk), dim3(256), 0, st, x, P, C, TC, rows, parts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_sum_parts(parts, (int)nblk, C, out, accumulate, st);
+  return launch_sum_parts(parts, (int)nblk, C, out, accumulate, st, tmp);
 }
 
 // out[i] = sum_j parts[j * n + i]  (split-K reduction), out may accumulate
@@ -202,10 +227,42 @@ __global__ void sum_parts_kernel(const float* __restrict__ parts, int nparts, in
   out[i] = (accumulate ? out[i] : 0.f) + (float)s;
 }
 
-hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st) {
+// Two-level form for many partials: groups of 32 summed in parallel into
+// FP64 sub-totals, then the sub-totals (fixed order, deterministic).
+__global__ void sum_parts_group_kernel(const float* __restrict__ parts, int nparts, int64_t n, int group,
+                                       double* __restrict__ tmp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j0 = (int)blockIdx.y * group;
+  const int j1 = min(nparts, j0 + group);
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s += (double)parts[(int64_t)j * n + i];
+  tmp[(int64_t)blockIdx.y * n + i] = s;
+}
+
+__global__ void sum_subtotals_kernel(const double* __restrict__ tmp, int ng, int64_t n, float* __restrict__ out,
+                                     int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int g = 0; g < ng; ++g) s += tmp[(int64_t)g * n + i];
+  out[i] = (accumulate ? out[i] : 0.f) + (float)s;
+}
+
+hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st,
+                            double* tmp) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, parts, nparts, n, out,
-                     accumulate);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (tmp && nparts > 64) {
+    constexpr int group = 32;
+    const int ng = (nparts + group - 1) / group;
+    hipLaunchKernelGGL(sum_parts_group_kernel, dim3(nb, (unsigned)ng), dim3(256), 0, st, parts, nparts, n, group, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_subtotals_kernel, dim3(nb), dim3(256), 0, st, tmp, ng, n, out, accumulate);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(nb), dim3(256), 0, st, parts, nparts, n, out, accumulate);
   return hipGetLastError();
 }
 
