@@ -15,6 +15,7 @@ Extra objects in the line:
                 against the FP64 run for each per-cell moment
   adaptive      the same workload with step sizes chosen on the device
   tracers       the same workload with test particles in every field
+  resident_1d   the 1D workload (fields resident in one workgroup for all steps)
   diagnostics   tw_moments with every optional output
   scale_512cube the paper's momentum-space Gaussian problem at 512^3 (FP32)
   batched       the three-size 3D soliton ensemble advanced from one HIP graph
@@ -197,6 +198,36 @@ def run_tracers(wl, precision, steps, warmup, ntracer=64, seed=20231007):
             "timed": "tw_step_tracers only"}
 
 
+def run_1d(seed=0):
+    """The 1D workload (256 points, 64 realizations + classical field, 1000
+    steps, FP64): every field stays resident in one workgroup for all steps, so
+    HBM is touched only at the ends; reported with the FP64 arithmetic rate it
+    implies (about 230 FP64 operations per cell and step: four 256-point
+    transforms at 5 n log2 n / n, the drift and kick factors, density, Green's
+    function)."""
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    wl = dict(inputs.WORKLOADS["1d_n256"])
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision="fp64")
+    plan = Plan(p)
+    cl = torch.from_numpy(inputs.initial_field("1d_n256")).cuda()
+    psi = plan.sample(cl, seed)
+    clt = cl.clone()
+    plan.step(psi, 10, wl["dt"], clt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(psi, wl["nsteps"], wl["dt"], clt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.close()
+    rate = p.n_real * p.ncell * wl["nsteps"] / el
+    flops = 4 * 5 * 8 + 70   # per cell and step
+    return {"workload": "1d_n256", "value": rate, "unit": METRIC, "seconds": el, "steps": wl["nsteps"],
+            "fp64_tflops_estimate": rate * flops / 1e12, "fp64_peak_tflops": 78.6}
+
+
 def run_diagnostics(wl, precision, seed=20231007, reps=3):
     """tw_moments with every optional output (energies, per-mode occupations,
     amplitude and phase spread) on the sampled workload ensemble."""
@@ -352,6 +383,7 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-tracers", action="store_true")
     ap.add_argument("--no-diagnostics", action="store_true")
+    ap.add_argument("--no-1d", dest="no_1d", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
@@ -390,6 +422,7 @@ def main():
         out["fp32_split"] = {
             "value": r32["value"], "ms_per_step": r32["ms_per_step"], "speedup": r32["value"] / main_run["value"],
             "roofline_frac": r32["roofline"]["frac"], "kernel": r32["roofline"]["kernel"],
+            "strided_pass_variant": r32["strided_variant"],
             "err_vs_fp64": {k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")},
         }
         log(f"fp32: {r32['value']:.4e}, errors {out['fp32_split']['err_vs_fp64']}")
@@ -405,6 +438,9 @@ def main():
         out["tracers"] = run_tracers(wl, args.precision, args.steps, args.warmup)
         out["tracers"]["fixed_step_ms_per_step"] = main_run["ms_per_step"]
         log(f"tracers: {out['tracers']}")
+    if not args.no_1d:
+        out["resident_1d"] = run_1d()
+        log(f"1d: {out['resident_1d']}")
     if not args.no_diagnostics:
         out["diagnostics"] = run_diagnostics(wl, args.precision)
         log(f"diagnostics: {out['diagnostics']}")

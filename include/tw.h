@@ -193,11 +193,15 @@ int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
 
 /* Autotune the kernel organisation of the passes along strided axes (y, z).
  * Returns at once if the plan's choice is already settled (tuning cache entry,
- * TW_COLS_VARIANT override, or an earlier call). Otherwise it times both
- * available organisations (on the strided passes a step runs: all of them, or
- * only the Poisson pass under the D = 2 alternating-storage schedule) on
- * scratch buffers of this plan's shape
- * (up to 32 pairs of realizations; allocates and frees them), keeps the faster
+ * TW_COLS_VARIANT override, or an earlier call). Optional: TW_STREAMS=2 in the
+ * environment makes tw_step run two halves of the pairs on two streams (+1-2%
+ * on the 2D workload; off by default because overlapping kernels make
+ * per-kernel timings meaningless). Otherwise it times both
+ * available organisations on the strided passes a step runs: all of them on a
+ * scratch ensemble of this plan's shape (up to 32 pairs of realizations,
+ * allocated and freed here), or, under the D = 2 alternating-storage schedule,
+ * only the Poisson pass on the plan's own spectral scratch at full size (its
+ * contents are overwritten; no field is touched). It keeps the faster
  * for this plan and records it in the tuning cache ($TW_TUNE_CACHE, else
  * $XDG_CACHE_HOME or $HOME/.cache, file twa_mi355x_tune.json), which later
  * tw_plan_create calls with the same device, grid, precision and ensemble

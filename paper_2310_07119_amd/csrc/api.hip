@@ -90,6 +90,9 @@ void free_plan(Plan* P) {
   if (P->phase) (void)hipFree(P->phase);
   if (P->z) (void)hipFree(P->z);
   if (P->psi_alt) (void)hipFree(P->psi_alt);
+  if (P->side) (void)hipStreamDestroy(P->side);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->rho_mean) (void)hipFree(P->rho_mean);
   if (P->partial) (void)hipFree(P->partial);
   if (P->scratch_small) (void)hipFree(P->scratch_small);
@@ -207,8 +210,12 @@ double kinetic_dt_bound(const Plan& P) {
 // The launch sequence of tw_step / tw_step_adaptive on stream s (arguments
 // already validated). With `ad`, the kick factor and the drift tables of every
 // step come from device memory, written by launch_adapt after each kick pass.
+// With prepare = false the tables and density means are taken as already
+// built (by an earlier call with prepare = true on a stream this one waits
+// for); [pair_lo, pair_hi) limits the pairs advanced (pair_hi < 0: all).
 int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hipStream_t s,
-                 const Adapt* ad = nullptr, const Tracers* tc = nullptr) {
+                 const Adapt* ad = nullptr, const Tracers* tc = nullptr, bool prepare = true, int64_t pair_lo = 0,
+                 int64_t pair_hi = -1) {
   const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
   const double h = 0.5 * dt;
   // drift tables: slot (axis, 0) = half step, (axis, 1) = full step
@@ -223,13 +230,13 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   auto ph_step = [&](int axis, int64_t st, bool last) -> const void* {
     return ad ? adapt_slot((int)(st % 2), axis) : phase_slot(axis, last ? 0 : 1);
   };
-  if (!ad) {
+  if (!ad && prepare) {
     for (int d = 0; d < P.dim; ++d) {
       TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, h, phase_slot(d, 0), s); }));
       TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_phase_table(P, d, dt, phase_slot(d, 1), s); }));
     }
   }
-  if (P.fp32)
+  if (P.fp32 && prepare)
     TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
   const double kick = dt / P.p.hbar_m;
 
@@ -246,6 +253,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   const int D = P.dim;
   const int64_t npairs = (nfield + 1) / 2;
   const int64_t chunk = ad ? npairs : (P.chunk_pairs > 0 ? P.chunk_pairs : default_chunk_pairs(P));
+  const int64_t plo = pair_lo, phi = pair_hi < 0 ? npairs : std::min<int64_t>(pair_hi, npairs);
   if (ad) {
     // max |V| of the initial fields (the potential passes of the energy), then
     // the sizes of steps 0 and 1 and their drift tables
@@ -293,8 +301,8 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
     // into the caller's buffer, x-contiguous.
     char* alt = static_cast<char*>(P.psi_alt);
     void* buf[2][2] = {{psi, psi_cl}, {alt, alt + P.elem * (size_t)P.p.n_real * (size_t)P.ncell}};
-    for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
-      const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
+    for (int64_t c0 = plo; c0 < phi; c0 += chunk) {
+      const int64_t nc = std::min<int64_t>(chunk, phi - c0);
       int cur = 0;  // buffer holding the fields
       // pass along physical axis `ax` over data stored `contig`-contiguous
       auto go = [&](int mode, int contig, int ax, const void* phase, int t_psi, int64_t kick_step = -1) {
@@ -344,8 +352,8 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
   }
   // Realizations are independent: each chunk of pairs runs every step before
   // the next chunk starts.
-  for (int64_t c0 = 0; c0 < npairs; c0 += chunk) {
-    const int64_t nc = std::min<int64_t>(chunk, npairs - c0);
+  for (int64_t c0 = plo; c0 < phi; c0 += chunk) {
+    const int64_t nc = std::min<int64_t>(chunk, phi - c0);
     auto run = [&](int mode, int axis, const void* phase) { return pass(P, a, mode, axis, phase, s, c0, nc); };
     int o[3] = {0, 1, 2};
     // opening half drift: every axis but o[0] plain, o[0] fused with the density transform
@@ -438,6 +446,8 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   P->npairs = (P->nfield + 1) / 2;
   P->chunk_pairs = 0;  // 0: default_chunk_pairs
   if (const char* env = getenv("TW_CHUNK_PAIRS")) P->chunk_pairs = atoll(env);
+  P->split_streams = 0;
+  if (const char* env = getenv("TW_STREAMS")) P->split_streams = atoi(env) >= 2;
   P->transpose2d = pr->dim == 2 ? 1 : 0;  // 2D: alternating storage, every pass reads rows
   if (const char* env = getenv("TW_TRANSPOSE")) P->transpose2d = pr->dim == 2 && atoi(env) != 0;
   // strided-pass organisation: tuning cache if it has this shape, else the
@@ -575,7 +585,29 @@ int tw_step(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, vo
   if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(TW_EINVAL, "dt must be finite");
   if (nsteps == 0) return TW_OK;
-  return enqueue_step(P, psi, psi_cl, nsteps, dt, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (P.split_streams && P.dim >= 2 && P.npairs >= 2 && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+      cap == hipStreamCaptureStatusNone) {
+    // two halves of the pairs on two streams: their passes overlap, so one
+    // half's strided Poisson pass runs beside the other half's row passes
+    if (!P.side) {
+      TW_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+      TW_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
+      TW_HIP(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
+    }
+    const int64_t nfield = P.p.n_real + (psi_cl ? 1 : 0);
+    const int64_t half = ((nfield + 1) / 2) / 2;
+    if (int rc = enqueue_step(P, psi, psi_cl, nsteps, dt, s, nullptr, nullptr, true, 0, 0)) return rc;
+    TW_HIP(hipEventRecord(P.ev_fork, s));
+    TW_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+    if (int rc = enqueue_step(P, psi, psi_cl, nsteps, dt, P.side, nullptr, nullptr, false, half, -1)) return rc;
+    if (int rc = enqueue_step(P, psi, psi_cl, nsteps, dt, s, nullptr, nullptr, false, 0, half)) return rc;
+    TW_HIP(hipEventRecord(P.ev_join, P.side));
+    TW_HIP(hipStreamWaitEvent(s, P.ev_join, 0));
+    return TW_OK;
+  }
+  return enqueue_step(P, psi, psi_cl, nsteps, dt, s);
 }
 
 int tw_step_tracers(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, double dt, double* tracers,
@@ -700,19 +732,25 @@ int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream) {
     if (variant_out) *variant_out = P.cols_variant;
     return TW_OK;
   }
-  // scratch ensemble of up to 32 pairs (enough workgroups to fill the device)
-  const int64_t npt = std::min<int64_t>(P.npairs, 32);
+  // Under the 2D alternating schedule only the Poisson pass is strided and it
+  // touches only the pair scratch: time it on the plan's own scratch at full
+  // size. Otherwise time every strided pass on a scratch ensemble of up to 32
+  // pairs (enough workgroups to fill the device).
+  const bool z_only = P.dim == 2 && P.transpose2d;
+  const int64_t npt = z_only ? P.npairs : std::min<int64_t>(P.npairs, 32);
   const int64_t nf = 2 * npt;
   void* tmp = nullptr;
-  if (hipMalloc(&tmp, (size_t)nf * P.ncell * P.elem) != hipSuccess) {
+  if (!z_only && hipMalloc(&tmp, (size_t)nf * P.ncell * P.elem) != hipSuccess) {
     (void)hipGetLastError();
     return fail(TW_ENOMEM, "autotune scratch allocation failed");
   }
   struct Free {
     void* p;
-    ~Free() { (void)hipFree(p); }
+    ~Free() {
+      if (p) (void)hipFree(p);
+    }
   } guard{tmp};
-  TW_HIP(hipMemsetAsync(tmp, 0, (size_t)nf * P.ncell * P.elem, s));
+  if (tmp) TW_HIP(hipMemsetAsync(tmp, 0, (size_t)nf * P.ncell * P.elem, s));
   TW_HIP(hipMemsetAsync(P.z, 0, (size_t)npt * P.ncell * P.elem, s));
   auto phase_slot = [&](int axis, int full) -> void* {
     return reinterpret_cast<char*>(P.phase) + sizeof(double) * 2 * (size_t)P.nmax * (2 * axis + full);
@@ -733,7 +771,7 @@ int tw_plan_autotune(tw_plan plan, int32_t* variant_out, void* stream) {
   // the strided passes a step runs: all five kinds, or with the 2D
   // alternating-storage schedule only the Poisson pass
   const int modes[5] = {PASS_ZPOISSON, PASS_DRIFT_RHO, PASS_KICK_DRIFT, PASS_DRIFT, PASS_ZFWD};
-  const int nmodes = (P.dim == 2 && P.transpose2d) ? 1 : 5;
+  const int nmodes = z_only ? 1 : 5;
   int rc = TW_OK;
   for (int v = 0; v < 2 && rc == TW_OK; ++v) {
     Q.cols_variant = v;

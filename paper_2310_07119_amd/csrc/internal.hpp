@@ -82,6 +82,9 @@ struct Plan {
   void* adapt_tab;       // cx<double>[3][3][nmax]: drift tables of the adaptive schedule
   int64_t chunk_pairs;   // pairs advanced through all steps together (cache residency)
   int transpose2d;       // 2D steps use the alternating-storage row schedule
+  int split_streams;     // tw_step runs two halves of the pairs on two streams
+  hipStream_t side;      // the second stream (created on first use, default priority)
+  hipEvent_t ev_fork, ev_join;
   int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
   int32_t tuned;         // cols_variant came from a measurement or the tuning cache
   // kernel timing (tw_plan_set_profiling)
