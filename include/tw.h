@@ -27,6 +27,10 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = legacy default stream);
  *    every device call is enqueued on it and the call returns without waiting.
  *    Device faults surface as TW_EHIP on a later call.
+ *  - A plan's workspace (spectral scratch, second field buffer, step tables,
+ *    adaptive-step state, reduction partials) is shared by all its calls:
+ *    calls on one plan must be ordered, e.g. issued on one stream. Different
+ *    plans are independent.
  */
 #ifndef TW_H
 #define TW_H
