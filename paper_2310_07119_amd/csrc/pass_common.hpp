@@ -28,16 +28,18 @@ __host__ __device__ constexpr int pencils_per_group() {
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (id mod 8), each with
-// its own L2. Strided passes touch every row of the field in short segments, so
-// the blocks reading neighbouring segments of the same rows should share one
-// XCD and run at about the same time: groups of G = 8 consecutive logical
-// blocks (512 contiguous bytes of each row at 64 bytes per block) are placed
-// on one XCD: physical 8k + x -> logical 64(k / 8) + 8x + (k mod 8). Grids that
-// are not a multiple of 64 blocks keep the identity. (Measured on MI355X for
-// the 512^2 passes: groups of 8 beat pairs by 3-5%.)
+// its own L2. Passes touch every row of the field in short segments (strided
+// reads, transposed stores), so the blocks reading neighbouring segments of the
+// same rows should share one XCD and run at about the same time: groups of G
+// consecutive logical blocks are placed on one XCD, physical 8k + x ->
+// logical 8G (k / G) + G x + (k mod G), with the largest G in {16, 8, 4, 2}
+// that divides the grid into whole rounds (else the identity). Measured on
+// MI355X for the 512^2 passes: groups of 8 beat pairs by 3-5%, groups of 16
+// beat 8 by another 1% (FP64).
 __device__ __forceinline__ unsigned xcd_group_remap(unsigned b, unsigned nb) {
-  constexpr unsigned G = 8;
-  if (nb % (8 * G) != 0) return b;
+  unsigned G = 16;
+  while (G >= 2 && nb % (8 * G) != 0) G >>= 1;
+  if (G < 2) return b;
   const unsigned k = b >> 3, x = b & 7;
   return (k / G) * (8 * G) + x * G + (k % G);
 }
