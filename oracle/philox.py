@@ -116,8 +116,9 @@ def cos_sin_turn(u):
     ps = np.ones_like(theta)
     pc = np.ones_like(theta)
     for k in range(10, 0, -1):
-        ps = 1.0 - (ps * th2) / float((2 * k) * (2 * k + 1))
-        pc = 1.0 - (pc * th2) / float((2 * k - 1) * (2 * k))
+        # multiply by the correctly rounded reciprocal of the factorial ratio
+        ps = 1.0 - (ps * th2) * (1.0 / float((2 * k) * (2 * k + 1)))
+        pc = 1.0 - (pc * th2) * (1.0 / float((2 * k - 1) * (2 * k)))
     s = theta * ps
     c = pc
     quad = q.astype(np.int64) & 3

@@ -13,8 +13,9 @@
 //   ln u  : u = m 2^e, m in [sqrt(1/2), sqrt(2)), s = (m-1)/(m+1),
 //           ln m = 2 s sum_{k<=12} s^{2k}/(2k+1) (Horner from k = 12), ln u = e ln2 + ln m;
 //   angle : t = 4 u2, q = floor(t), f = t - q, f > 1/2 -> (f - 1, q + 1), theta = f pi/2;
-//           sin theta = theta prod-form Taylor series to theta^21, cos theta to theta^20,
-//           rotated by q quarter turns.
+//           sin theta = theta prod-form Taylor series to theta^21, cos theta to theta^20
+//           (each factor multiplies by the correctly rounded reciprocal of
+//           (2k)(2k+1) or (2k-1)(2k)), rotated by q quarter turns.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -87,9 +88,11 @@ __device__ void cos_sin_turn(double u, double* c_out, double* s_out) {
   const double th = f * kHalfPi;
   const double th2 = th * th;
   double ps = 1.0, pc = 1.0;
+#pragma unroll
   for (int k = 10; k >= 1; --k) {
-    ps = 1.0 - (ps * th2) / (double)((2 * k) * (2 * k + 1));
-    pc = 1.0 - (pc * th2) / (double)((2 * k - 1) * (2 * k));
+    // times the correctly rounded reciprocal of the factorial ratio (a constant)
+    ps = 1.0 - (ps * th2) * (1.0 / (double)((2 * k) * (2 * k + 1)));
+    pc = 1.0 - (pc * th2) * (1.0 / (double)((2 * k - 1) * (2 * k)));
   }
   const double s = th * ps;
   const double c = pc;
