@@ -133,3 +133,25 @@ def test_2d_schedules_vs_oracle(precision, nsteps, transpose, monkeypatch):
     assert rel(g["cl"], cl) < tol
     for r in (0, 17, 40):
         assert rel(g["psi"][r], psi[r]) < tol, r
+
+
+@pytest.mark.parametrize("transpose", ["0", "1"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(96, 48), (48, 192), (1024, 32), (24, 384)], ids=lambda n: "x".join(map(str, n)))
+def test_2d_mixed_radix_and_long_axes(n, precision, transpose, monkeypatch):
+    """Lengths 3 * 2^k and the longest supported axis (1024, sixteen points per
+    thread) in both 2D schedules, on non-square grids (the alternating schedule
+    swaps the roles of the axes every step)."""
+    monkeypatch.setenv("TW_TRANSPOSE", transpose)
+    box = (1.0, n[1] / n[0])
+    p = Problem(n=n, box=box, hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=1e5, n_real=5, precision=precision)
+    psi_cl = inputs.lognormal_field(n, box, kcut=min(n) // 4, seed=8)
+    nsteps, dt = 5, 1e-4
+    print(f"2d mixed radix {n} {precision} transpose={transpose}", flush=True)
+    g = gpu_run(p, psi_cl, 99, nsteps, dt)
+    prob = oracle_problem(p)
+    psi = tw.evolve(prob, g["psi0"].astype(np.complex128), nsteps, dt)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64).astype(np.complex128)
+    tol = TOL[precision]
+    assert rel(g["psi"], psi) < tol
+    assert rel(g["cl"], tw.evolve(prob, cl0, nsteps, dt)) < tol
