@@ -74,6 +74,29 @@ def measured_traffic(kind, precision, workload):
     return d.get("traffic_bytes_per_launch")
 
 
+def stream_bandwidth():
+    """Best read+write streaming rate this device reaches in a plain kernel
+    (torch.add over 1 GiB in and 1 GiB out), GB/s: the practical ceiling next
+    to the 8 TB/s published peak."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.add(x, 1.0, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        torch.add(x, 1.0, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
+
+
 def run_gpu(wl, precision, steps, warmup, seed=20231007):
     import torch
     from paper_2310_07119_amd import Plan, Problem, inputs
@@ -412,7 +435,7 @@ def main():
                    "G": wl["G"], "m_tot": wl["m_tot"], "precision": args.precision,
                    "timed": "tw_sample + K tw_step leapfrog steps + tw_moments (with energies)",
                    "classical_field": "evolved alongside, not counted in the work"},
-        "roofline": main_run["roofline"],
+        "roofline": dict(main_run["roofline"], stream_measured_gbs=stream_bandwidth()),
         "kernel_ms": main_run["kernel_ms"],
         "strided_pass_variant": main_run["strided_variant"],
     }
