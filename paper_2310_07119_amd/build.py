@@ -11,12 +11,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtw.so")
+EXAMPLE = os.path.join(PKG, "tw_c_example")
 BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
-          # packed FP32 instructions stay off (see DESIGN: correctness of some forms)
+          # packed FP32 instructions stay off: some of their forms have given wrong results on this hardware
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
 # The sampler must not contract a*b+c into fma: its draws are defined as a
@@ -46,6 +47,14 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    # a host program that uses the C ABI directly (tests/c_abi_example.cpp)
+    example = os.path.join(ROOT, "tests", "c_abi_example.cpp")
+    if os.path.exists(example):
+        cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), example, "-o", EXAMPLE,
+               "-L", PKG, "-ltw", "-Wl,-rpath,$ORIGIN"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"C ABI example build failed:\n{r.stderr}")
     if verbose:
         print(f"built {OUT}")
     return OUT
