@@ -26,8 +26,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   const int64_t p = (int64_t)grp * C + c;
   const bool active = p < npencils;
   const int64_t pp = active ? p : 0;
-  const int64_t base = (pp % a.stride) + (pp / a.stride) * a.stride * N;
-  const int64_t stride = a.stride;
+  // FP64 row passes (always along the contiguous axis: stride 1, checked by
+  // the launchers) take the stride as a constant: the 64-bit address
+  // arithmetic folds away, which brings the drift+density pass to three
+  // wavefronts per SIMD (4% faster on MI355X). The FP32 row passes ran 9%
+  // slower in the kick pass with it and keep the runtime stride.
+  constexpr bool UNIT = ROWS && sizeof(T) == 8;
+  const int64_t stride = UNIT ? 1 : a.stride;
+  const int64_t base = UNIT ? pp * N : (pp % stride) + (pp / stride) * stride * N;
   const int64_t pair = a.pair0 + by;
   const int64_t fA = 2 * pair, fB = 2 * pair + 1;
   const bool hasB = fB < a.nfield;
