@@ -128,7 +128,7 @@ int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double
  *   dt_max  : > 0, upper bound on every step (also the step when nothing else binds).
  *   courant : c_f in (0, 1].
  *   dt_out  : device, [nsteps] doubles receiving dt_n (the elapsed time is their
- *             sum), or NULL.
+ *             sum), or NULL; 8-byte aligned (else TW_ELAYOUT).
  * D >= 2 only (TW_EUNSUPPORTED for D = 1, whose fields are advanced by a
  * resident kernel that never leaves the workgroup). Other arguments as tw_step. */
 int tw_step_adaptive(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt_max,
@@ -153,7 +153,8 @@ int tw_step_tracers(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps
  * particle i (k < D positions, then D velocities); the per-axis uncertainty
  * product is sqrt(out[i][d] * out[i][D + d]).
  *   tracers : device, [>= n_real][ntracer][2 D] doubles.
- *   out     : device, [ntracer][2 D] doubles. */
+ *   out     : device, [ntracer][2 D] doubles.
+ * Both 8-byte aligned (else TW_ELAYOUT); NULL or ntracer < 1 gives TW_EINVAL. */
 int tw_tracer_spread(tw_plan plan, const double* tracers, int64_t ntracer, double* out, void* stream);
 
 /* Outputs of tw_moments. Every pointer is a caller-owned device array and may

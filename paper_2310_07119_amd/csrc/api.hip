@@ -632,6 +632,8 @@ int tw_tracer_spread(tw_plan plan, const double* tracers, int64_t ntracer, doubl
   if (!plan) return fail(TW_EINVAL, "NULL plan");
   Plan& P = *reinterpret_cast<Plan*>(plan);
   if (!tracers || !out || ntracer < 1) return fail(TW_EINVAL, "bad tracer spread arguments");
+  if (reinterpret_cast<uintptr_t>(tracers) % 8 != 0 || reinterpret_cast<uintptr_t>(out) % 8 != 0)
+    return fail(TW_ELAYOUT, "tracers and out must be 8-byte aligned");
   TW_HIP(launch_tracer_spread(P, tracers, ntracer, out, reinterpret_cast<hipStream_t>(stream)));
   return TW_OK;
 }
@@ -645,6 +647,7 @@ int tw_step_adaptive(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, doub
   if (nsteps < 0) return fail(TW_EINVAL, "nsteps must be >= 0");
   if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(TW_EINVAL, "dt_max must be positive and finite");
   if (!(courant > 0.0) || !(courant <= 1.0)) return fail(TW_EINVAL, "courant must be in (0, 1]");
+  if (reinterpret_cast<uintptr_t>(dt_out) % 8 != 0) return fail(TW_ELAYOUT, "dt_out must be 8-byte aligned");
   if (P.dim < 2 || !P.z || !P.adapt) return fail(TW_EUNSUPPORTED, "adaptive steps need D >= 2 (all axes >= 16 points)");
   if (P.chunk_pairs > 0 && P.chunk_pairs < P.npairs)
     return fail(TW_EUNSUPPORTED, "adaptive steps need the whole ensemble in one chunk (TW_CHUNK_PAIRS)");
