@@ -19,6 +19,8 @@ CASES = [
     ((32, 128), 2, 10, 2e-4, 0.5, 3.0, 10.0, 1e5),          # 2D, long y axis
     ((16, 16, 32), 3, 6, 2e-4, 1.0, 1.0, 20.0, 1e6),        # 3D
     ((32, 16, 16), 4, 5, 1e-4, 1.0, 2.0, 10.0, 1e6),        # 3D, x longest
+    ((48, 24), 1, 8, 2e-4, 0.7, 0.0, 1.0, 1e3),             # 2D, one realization, G = 0 (free field), 3*2^k axes
+    ((16, 24, 16), 1, 4, 2e-4, 1.0, 1.5, 8.0, 1e4),         # 3D, one realization, mixed radix y
 ]
 
 
@@ -62,8 +64,16 @@ def test_sample_step_moments_vs_oracle(case, precision, variant, monkeypatch):
     ref = tw.moments(prob, psi, n_tot, cl, modes=True, decoherence_=True)
     m = g["mom"]
     for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "mode_occ", "var_amp", "var_phase", "norm", "energy"):
+        if nr == 1 and k in ("var_rho", "var_amp", "var_phase"):
+            # one realization: spreads are zero up to rounding on both sides
+            assert np.max(np.abs(m[k])) < 1e-12 and np.max(np.abs(ref[k])) < 1e-12, k
+            continue
         assert rel(m[k], ref[k]) < tol * 10, k
     for k in ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "Var_A", "Var_phi"):
+        if nr == 1 and k in ("Q_raw", "Var_A", "Var_phi"):
+            # one realization: these are differences of equal quantities, zero up to rounding
+            assert abs(m[k]) < 1e-12 and abs(ref[k]) < 1e-12, k
+            continue
         assert abs(m[k] - ref[k]) <= tol * 10 * max(abs(ref[k]), 1e-300) + 1e-300, k
     assert abs(m["energy_mean"] - ref["energy"].mean()) < tol * 10 * abs(ref["energy"].mean())
     assert abs(m["energy_classical"] - tw.energy(prob, cl)) < tol * 10 * abs(tw.energy(prob, cl))
