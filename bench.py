@@ -381,6 +381,29 @@ def _oracle_steps(args):
     return psi.shape[0] * prob.grid.ncell * steps, steps, time.perf_counter() - t0
 
 
+def _fno_oracle_times(seed=5):
+    """The surrogate's oracle (numpy, BF16 operands emulated) on one 256^2
+    field of the surrogate study's shape, one BLAS thread: seconds for a
+    forward pass and for a backward pass (which includes its forward)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fno_oracle as fo
+    cfg = fo.Config(H=256, W=256, c_in=4, width=32, mx=16, my=16, layers=4, proj=128, c_out=2)
+    params = fo.init_params(cfg, seed)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((1, cfg.H, cfg.W, cfg.c_in))
+    dy = rng.standard_normal((1, cfg.H, cfg.W, cfg.c_out))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fo.forward(cfg, params, x)
+        t1 = time.perf_counter()
+        fo.backward(cfg, params, x, dy)
+        t2 = time.perf_counter()
+    return {"forward_s": t1 - t0, "forward_backward_s": t2 - t1, "threads": 1,
+            "field": "256x256, 4 input channels, width 32, 4 Fourier layers of 32x16 modes, projection 128"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -452,16 +475,17 @@ def cpu_baseline(wl, budget_s=15.0, n_sample_real=4, seed=20231007, max_workers=
             if len(res) == workers:
                 allc = sum(w / e for w, _, e in res)
                 steps_w = min(st for _, st, _ in res)
+    fno = _fno_oracle_times()
     model = _cpu_model()
     sample = (f"{n_sample_real} realizations x {steps1} leapfrog steps of the {wl['name']} grid "
               f"{'x'.join(map(str, wl['n']))} (numpy FP64), {el1:.1f} s on one thread")
     if allc is None:
         return {"value": single, "unit": METRIC, "cores": 1, "kind": "oracle", "sample": sample + f"; {model}",
-                "nproc": ncpu}
+                "nproc": ncpu, "fno_oracle": fno}
     sample += (f"; then {workers} worker processes, each stepping its own copy of the sample (>= {steps_w} "
                f"steps in about {budget_s:.0f} s); {model}")
     return {"value": allc, "unit": METRIC, "cores": workers, "kind": "oracle", "sample": sample,
-            "single_thread_value": single, "nproc": ncpu}
+            "single_thread_value": single, "nproc": ncpu, "fno_oracle": fno}
 
 
 def rel(a, b):
