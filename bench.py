@@ -503,6 +503,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-grf128", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-tracers", action="store_true")
     ap.add_argument("--no-diagnostics", action="store_true")
@@ -570,6 +571,16 @@ def main():
     if not args.no_scale:
         out["scale_512cube"] = run_scale(max(args.steps // 5, 2))
         log(f"scale: {out['scale_512cube']}")
+    if not args.no_grf128:
+        # one 3D plan: the 128^3 Gaussian-random-field ensemble, FP32 split
+        w3 = dict(inputs.WORKLOADS["3d_n128_grf"], name="3d_n128_grf")
+        r3 = run_gpu(w3, "fp32", max(args.steps // 2, 5), 2)
+        out["grf_128cube"] = {"workload": "3d_n128_grf", "grid": list(w3["n"]), "n_real": w3["n_real"],
+                              "precision": "fp32", "value": r3["value"], "unit": METRIC,
+                              "ms_per_step": r3["ms_per_step"], "roofline": r3["roofline"],
+                              "kernel_ms": r3["kernel_ms"], "strided_pass_variant": r3["strided_variant"],
+                              "timed": "tw_sample + K tw_step leapfrog steps + tw_moments (with energies)"}
+        log(f"grf_128cube: {out['grf_128cube']}")
     if not args.no_batched:
         out["batched"] = run_batched(max(args.steps // 2, 1), 1)
         log(f"batched: {out['batched']}")

@@ -544,7 +544,7 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   const int64_t nwaves = (P->ncell + 63) / 64;
   const int64_t energy_part = 4 * P->nfield * gmax + P->nfield;
   const int64_t mom_part = pr->n_real * nwaves + 3 * nwaves + pr->n_real + 8 + 2 * nwaves;
-  P->partial_len = (size_t)(energy_part + mom_part);
+  P->partial_len = (size_t)std::max<int64_t>(energy_part + mom_part, P->nfield * kFieldMeanParts);
   ALLOC(P->partial, sizeof(double) * P->partial_len);
   ALLOC(P->scratch_small, sizeof(double) * 64);
   if (pr->dim >= 2) {

@@ -11,6 +11,7 @@ namespace tw {
 // Arguments of one pencil pass over the ensemble (see kernels_step.hip).
 constexpr int kVmaxBuckets = 64;     // atomic-max slots per recorded maximum
 constexpr int kAdaptScalars = 16;    // adaptive-step state before the max|V| buckets
+constexpr int kFieldMeanParts = 64;  // partial sums per field of the mean-density reduction
 
 struct PassArgs {
   void* psi;               // [n_real][N] fields (plan precision)

@@ -336,28 +336,54 @@ hipError_t launch_adapt(const Plan& P, int64_t step, int last_next, double dt_ma
   return hipGetLastError();
 }
 
-// mean density m_tot * sum_g |psi_g|^2 / N of every field, FP64.
+// Mean density m_tot * sum_g |psi_g|^2 / N of every field, FP64, in two
+// launches: kFieldMeanParts workgroups per field sum consecutive chunks of it
+// (enough workgroups to stream the ensemble at full bandwidth), then one
+// thread per field adds its partial sums in a fixed order.
 template <class T>
-__global__ void __launch_bounds__(256) field_mean_kernel(const void* psi, const void* psi_cl, int64_t n_real,
-                                                         int64_t ncell, double m_tot, double* out) {
+__global__ void __launch_bounds__(256) field_mean_parts_kernel(const void* psi, const void* psi_cl, int64_t n_real,
+                                                               int64_t ncell, int64_t chunk, int nb, double* parts) {
   __shared__ double red[4];
-  const int64_t f = blockIdx.x;
+  const int64_t f = blockIdx.x / nb;  // block f * nb + b sums chunk b of field f
+  const int64_t b = blockIdx.x % nb;
   const cx<T>* fp = f < n_real ? reinterpret_cast<const cx<T>*>(psi) + f * ncell : reinterpret_cast<const cx<T>*>(psi_cl);
+  const int64_t g0 = b * chunk;
+  const int64_t g1 = g0 + chunk < ncell ? g0 + chunk : ncell;
   double s = 0.0;
-  for (int64_t g = threadIdx.x; g < ncell; g += blockDim.x) s += (double)abs2(fp[g]);
+#pragma unroll 4
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) s += (double)abs2(fp[g]);
   s = block_sum(s, red);
-  if (threadIdx.x == 0) out[f] = m_tot * s / (double)ncell;
+  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+__global__ void field_mean_finish_kernel(const double* parts, int nb, int64_t nfield, int64_t ncell, double m_tot,
+                                         double* out) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfield) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += parts[f * nb + b];
+  out[f] = m_tot * s / (double)ncell;
 }
 
 hipError_t launch_field_mean(const Plan& P, const void* psi, const void* psi_cl, int64_t nfield, double* out,
                              hipStream_t s) {
   if (nfield <= 0) return hipSuccess;
+  // chunks of at least 16 elements per thread, at most kFieldMeanParts per field;
+  // the plan's partial-sum buffer holds nfield * kFieldMeanParts doubles
+  int64_t nb = (P.ncell + 4095) / 4096;
+  if (nb > kFieldMeanParts) nb = kFieldMeanParts;
+  if (nb < 1) nb = 1;
+  const int64_t chunk = (P.ncell + nb - 1) / nb;
+  if ((size_t)(nfield * nb) > P.partial_len) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(nfield * nb));
   if (P.fp32)
-    hipLaunchKernelGGL(field_mean_kernel<float>, dim3((unsigned)nfield), dim3(256), 0, s, psi, psi_cl,
-                       (int64_t)P.p.n_real, P.ncell, P.p.m_tot, out);
+    hipLaunchKernelGGL(field_mean_parts_kernel<float>, grid, dim3(256), 0, s, psi, psi_cl, (int64_t)P.p.n_real,
+                       P.ncell, chunk, (int)nb, P.partial);
   else
-    hipLaunchKernelGGL(field_mean_kernel<double>, dim3((unsigned)nfield), dim3(256), 0, s, psi, psi_cl,
-                       (int64_t)P.p.n_real, P.ncell, P.p.m_tot, out);
+    hipLaunchKernelGGL(field_mean_parts_kernel<double>, grid, dim3(256), 0, s, psi, psi_cl, (int64_t)P.p.n_real,
+                       P.ncell, chunk, (int)nb, P.partial);
+  hipLaunchKernelGGL(field_mean_finish_kernel, dim3((unsigned)((nfield + 255) / 256)), dim3(256), 0, s, P.partial,
+                     (int)nb, nfield, P.ncell, P.p.m_tot, out);
   return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 
 # kernel kinds (as reported by tw_plan_get_profile) -> pass mode in the
 # compiled kernel names (pass_kernel<T, N, MODE, ROWS> / cols_kernel<T, N, MODE>)
-KIND_MODES = {"pass_kick_drift": 5, "pass_drift_rho": 1, "pass_zpoisson": 3}
+KIND_MODES = {"pass_drift": 0, "pass_drift_rho": 1, "pass_zfwd": 2, "pass_zpoisson": 3, "pass_zinv": 4,
+              "pass_kick_drift": 5, "pass_rho": 6, "pass_kin_sum": 7, "pass_pot_sum": 8}
 SOURCES = ("csrc/fft.hpp", "csrc/common.hpp", "csrc/pass_common.hpp", "csrc/pass_rows.hpp", "csrc/pass_cols.hpp",
            "csrc/kernels_step.hip", "csrc/kernels_cols.hip")
 
@@ -120,8 +121,7 @@ def _kind_of(name):
     return ("fp64" if m.group(2) == "double" else "fp32"), int(m.group(4))
 
 
-MODE_KIND = {0: "pass_drift", 1: "pass_drift_rho", 2: "pass_zfwd", 3: "pass_zpoisson", 4: "pass_zinv",
-             5: "pass_kick_drift", 6: "pass_rho", 7: "pass_kin_sum", 8: "pass_pot_sum"}
+MODE_KIND = {m: k for k, m in KIND_MODES.items()}
 
 
 def kernels(a):
