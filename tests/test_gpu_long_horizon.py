@@ -1,0 +1,52 @@
+"""The 2D benchmark workload at its full size over its full horizon (512^2,
+256 realizations + classical field, 5000 steps of 1e-4): properties that hold
+at any size, since the oracle cannot follow this run step by step.
+
+* Every step is unitary, so each realization's norm is conserved up to
+  rounding (measured drift about 1.5e-12 after 5000 steps).
+* The split-step energy error is second order in the step: the classical
+  field's energy change at T = 0.5 shrinks four-fold when the step halves, and
+  the ensemble's energies change by far less than their size."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2310_07119_amd import Plan, Problem, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_full_horizon_norm_and_energy_order():
+    w = inputs.WORKLOADS["2d_n512_pair"]
+    p = Problem(n=w["n"], box=w["box"], hbar_m=w["hbar_m"], G=w["G"], m_tot=w["m_tot"], n_tot=w["n_tot"],
+                n_real=w["n_real"], precision="fp64")
+    cl = torch.from_numpy(inputs.initial_field("2d_n512_pair")).cuda()
+    plan = Plan(p)
+    plan.autotune()
+    T = 0.5
+    drift_cl = {}
+    for dt in (2e-4, 1e-4):
+        nsteps = int(round(T / dt))
+        print(f"full horizon: dt={dt} steps={nsteps}", flush=True)
+        psi = plan.sample(cl, 3)
+        clt = cl.clone()
+        m0 = plan.moments(psi, clt)
+        plan.step(psi, nsteps, dt, clt)
+        m1 = plan.moments(psi, clt)
+        n0, n1 = m0["norm"].cpu().numpy(), m1["norm"].cpu().numpy()
+        e0, e1 = m0["energy"].cpu().numpy(), m1["energy"].cpu().numpy()
+        assert m1["nonfinite"] == 0
+        assert np.max(np.abs(n1 / n0 - 1.0)) < 1e-10
+        assert np.max(np.abs(e1 / e0 - 1.0)) < 1e-6
+        drift_cl[dt] = m1["energy_classical"] - m0["energy_classical"]
+        del psi
+    ratio = drift_cl[2e-4] / drift_cl[1e-4]
+    assert 3.0 < ratio < 5.0, ratio
+    plan.close()
+    torch.cuda.empty_cache()
