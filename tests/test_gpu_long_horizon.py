@@ -50,3 +50,38 @@ def test_full_horizon_norm_and_energy_order():
     assert 3.0 < ratio < 5.0, ratio
     plan.close()
     torch.cuda.empty_cache()
+
+
+def test_3d_fp32_split_full_run_against_fp64():
+    """The 3D 128^3 workload (64 realizations, 2000 steps of 1e-4) in the FP32
+    split form against the same run in FP64: per-cell moments, norms and
+    energies agree normwise to 2e-3 at the end (measured at most 5.5e-4, for
+    Var rho), and the FP64 norms are conserved to 1e-10."""
+    w = inputs.WORKLOADS["3d_n128_grf"]
+    cl = torch.from_numpy(inputs.initial_field("3d_n128_grf")).cuda()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        print(f"3d full run: {prec}", flush=True)
+        p = Problem(n=w["n"], box=w["box"], hbar_m=w["hbar_m"], G=w["G"], m_tot=w["m_tot"], n_tot=w["n_tot"],
+                    n_real=w["n_real"], precision=prec)
+        plan = Plan(p)
+        psi = plan.sample(cl, 9)
+        clt = cl.to(p.cdtype).clone()
+        n0 = plan.moments(psi, clt, energy=False)["norm"].cpu().numpy()
+        plan.step(psi, w["nsteps"], w["dt"], clt)
+        m = plan.moments(psi, clt)
+        assert m["nonfinite"] == 0
+        if prec == "fp64":
+            assert np.max(np.abs(m["norm"].cpu().numpy() / n0 - 1.0)) < 1e-10
+        out[prec] = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in m.items()}
+        plan.close()
+        del psi, clt
+        torch.cuda.empty_cache()
+
+    def rel(a, b):
+        return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
+        assert rel(out["fp32"][k], out["fp64"][k]) < 2e-3, k
+    for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2", "energy_classical"):
+        assert abs(out["fp32"][k] - out["fp64"][k]) < 2e-3 * abs(out["fp64"][k]), k
