@@ -123,3 +123,28 @@ def test_3d_subset_32cube_fp32_vs_oracle():
     om = tw.moments(prob, opsi, p.n_tot, ocl)
     for k in ("mean_rho", "var_rho", "mean_psi", "norm", "energy"):
         assert rel(m[k].cpu().numpy(), om[k]) < TOL["fp32"], k
+
+
+def test_3d_subset_32cube_fp64_full_horizon_vs_oracle():
+    """The same 32^3 regeneration over the workload's full horizon (2000 steps)
+    in FP64: three realizations and the classical field against the oracle at
+    1e-10 (a 1e-15 perturbation of the initial ensemble moves the oracle's
+    final state by 2e-14 over this horizon, so rounding is not amplified)."""
+    p, w = _problem("3d_n128_grf", "fp64", n=(32, 32, 32), n_real=3, n_tot=1e3 * 32 ** 3)
+    psi_cl = inputs.initial_field("3d_n128_grf", n=(32, 32, 32))
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 11)
+    clt = cl.clone()
+    plan.step(psi, w["nsteps"], w["dt"], clt)
+    m = plan.moments(psi, clt)
+    prob = oracle_problem(p)
+    opsi, ocl, om = tw.run(prob, psi_cl, p.n_real, p.n_tot, 11, w["nsteps"], w["dt"])
+    tol = TOL["fp64"]
+    assert rel(psi.cpu().numpy(), opsi) < tol
+    assert rel(clt.cpu().numpy(), ocl) < tol
+    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
+        assert rel(m[k].cpu().numpy(), om[k]) < 10 * tol, k
+    for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2"):
+        assert abs(m[k] - om[k]) < 10 * tol * abs(om[k]), k
+    plan.close()
