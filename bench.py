@@ -144,7 +144,9 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     traffic = measured_traffic(kind, precision, wl["name"])
     res["roofline"] = {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                       "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches}
+                       "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches,
+                       # compulsory bytes / bytes the counters saw move (1 = no wasted traffic)
+                       "pass_efficiency": (nbytes / traffic) if (nbytes and traffic) else None}
     res["kernel_ms"] = {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     res["strided_variant"] = variant
     plan.close()
