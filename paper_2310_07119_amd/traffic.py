@@ -187,6 +187,70 @@ def copy(a):
     print(f"copied {a.mib} MiB x3", flush=True)
 
 
+def counters(a):
+    """Per-dispatch SQ counters of the pass kernels of one precision and length
+    (several --pmc runs), with the derived figures rocprofv3 itself defines:
+    VALUBusy = SQ_ACTIVE_INST_VALU / CU_NUM / GRBM_GUI_ACTIVE(max), LDS active
+    likewise from SQ_LDS_IDX_ACTIVE, LDSBankConflict and conflicts per access
+    from SQ_LDS_BANK_CONFLICT. GRBM_GUI_ACTIVE is read as the sum over the XCD
+    instances (the per-XCD maximum is taken as sum / xcds)."""
+    ctype = "double" if a.precision == "fp64" else "float"
+    rows = []
+    for d in a.dirs:
+        rows.extend(_rows(d))
+    lines = [f"# SQ counters of the pass kernels: {a.title}", "", "Commands (from the repository root):", "", "```"]
+    lines += a.commands.splitlines() + ["```", ""]
+    lines += ["Per dispatch, averaged over the dispatches of each kernel; derived figures as rocprofv3 defines them",
+              f"(CU_NUM = {a.cus}, GRBM_GUI_ACTIVE summed over {a.xcds} XCDs).", ""]
+    names = sorted({r["Kernel_Name"] for r in rows if "pass_kernel" in r["Kernel_Name"] or "cols_kernel" in r["Kernel_Name"]})
+    names = [n for n in names if f"<{ctype}, {a.length}," in n]
+    table = ["| kernel | kind | dispatches | VALU busy | FP64 FLOP/s (TFLOP/s) | LDS active | LDS bank-conflict cycles | conflicts per LDS access |",
+             "|---|---|---:|---:|---:|---:|---:|---:|"]
+    for n in names:
+        mode = int(n.split(",")[2].split(">")[0].strip())
+        vals = {}
+        for cname in sorted({r["Counter_Name"] for r in rows if r["Kernel_Name"] == n}):
+            v = _per_dispatch(rows, cname, lambda k, n=n: k == n)
+            if v:
+                vals[cname] = sum(v) / len(v)
+        g = vals.get("GRBM_GUI_ACTIVE")
+        if not g:
+            continue
+        gmax = g / a.xcds
+        cyc = a.cus * gmax
+        valu = vals.get("SQ_ACTIVE_INST_VALU")
+        lds = vals.get("SQ_LDS_IDX_ACTIVE")
+        conf = vals.get("SQ_LDS_BANK_CONFLICT")
+        fl = None
+        if all(k in vals for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")):
+            fl = 64 * (vals["SQ_INSTS_VALU_ADD_F64"] + vals["SQ_INSTS_VALU_MUL_F64"] + 2 * vals["SQ_INSTS_VALU_FMA_F64"])
+        durs = {}
+        for r in rows:
+            if r["Kernel_Name"] == n:
+                durs[r.get("Dispatch_Id")] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        dur_s = sum(durs.values()) / len(durs)
+        f = lambda x, pct=True: "-" if x is None else (f"{100 * x:.1f}%" if pct else f"{x:.2f}")
+        table.append(f"| `{n[:52]}` | {MODE_KIND.get(mode, mode)} | {int(len(_per_dispatch(rows, 'GRBM_GUI_ACTIVE', lambda k, n=n: k == n)))} | "
+                     f"{f(valu / cyc if valu else None)} | {f(fl / dur_s / 1e12 if fl else None, False)} | "
+                     f"{f(lds / cyc if lds else None)} | {f(conf / cyc if conf else None)} | "
+                     f"{f(conf / (lds - conf) if (lds and conf) else None, False)} |")
+    lines += table
+    lines += ["", "FLOP/s: 64 lanes x (ADD_F64 + MUL_F64 + 2 FMA_F64) instructions over the dispatch's own "
+              "duration (its end minus start timestamp in the counter run); FP64 vector peak 78.6 TFLOP/s.", ""]
+    raw = ["| kernel | " + " | ".join(c.replace("SQ_", "").replace("GRBM_", "") for c in a.raw) + " |",
+           "|---|" + "---:|" * len(a.raw)]
+    for n in names:
+        cells = []
+        for cname in a.raw:
+            v = _per_dispatch(rows, cname, lambda k, n=n: k == n)
+            cells.append(f"{sum(v) / len(v):.4g}" if v else "-")
+        raw.append(f"| `{n[:52]}` | " + " | ".join(cells) + " |")
+    lines += ["Raw per-dispatch averages:", ""] + raw + [""]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(table))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -208,7 +272,22 @@ def main():
     k.add_argument("--bench-log", dest="bench_log", default="")
     k.add_argument("--timed-launches", dest="timed_launches", type=int, default=0)
     k.add_argument("--top", type=int, default=25)
+    q = sub.add_parser("counters")
+    q.add_argument("--dirs", nargs="+", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    q.add_argument("--length", type=int, default=512)
+    q.add_argument("--title", default="")
+    q.add_argument("--commands", default="")
+    q.add_argument("--cus", type=int, default=256)
+    q.add_argument("--xcds", type=int, default=8)
+    q.add_argument("--raw", nargs="*", default=["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS",
+                                                 "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS",
+                                                 "SQ_WAVES", "GRBM_GUI_ACTIVE"])
     a = ap.parse_args()
+    if a.cmd == "counters":
+        counters(a)
+        return 0
     if a.cmd == "copy":
         copy(a)
     elif a.cmd == "kernels":
