@@ -468,6 +468,10 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   } while (0)
 
   // twiddle and wavenumber tables per axis
+  // search radius of the FP32 twiddle rounding below (measured on the 3D
+  // 128^3 run: one unit takes the FP32 norm drift from 2.9e-5 to 2.0e-5 over
+  // 2000 steps; two or three units gain nothing more and lose angle accuracy)
+  constexpr int kTwiddleUlps = 1;
   for (int d = 0; d < 3; ++d) {
     const int n = P->n[d];
     std::vector<double> k2(n);
@@ -488,8 +492,34 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
       tw2[2 * e + 1] = (double)sinl(ang);
     }
     if (P->fp32) {
+      // FP32 twiddles: of the float pairs within kTwiddleUlps units in the
+      // last place of (cos, sin), the one whose modulus is closest to 1 (ties:
+      // the nearer pair), so that the FP32 transforms do not scale the fields
+      // systematically
       std::vector<float> tf(2 * n);
-      for (int i = 0; i < 2 * n; ++i) tf[i] = (float)tw2[i];
+      for (int e = 0; e < n; ++e) {
+        const float c0 = (float)tw2[2 * e], s0 = (float)tw2[2 * e + 1];
+        float bc = c0, bs = s0;
+        long double best_mod = -1.0L, best_dist = 0.0L;
+        auto step = [](float x, int k) {
+          for (int i = 0; i < (k < 0 ? -k : k); ++i) x = std::nextafter(x, k > 0 ? 2.0f : -2.0f);
+          return x;
+        };
+        for (int dc = -kTwiddleUlps; dc <= kTwiddleUlps; ++dc)
+          for (int ds = -kTwiddleUlps; ds <= kTwiddleUlps; ++ds) {
+            const float c = step(c0, dc), sn = step(s0, ds);
+            const long double mod = fabsl((long double)c * c + (long double)sn * sn - 1.0L);
+            const long double dist = fabsl((long double)c - tw2[2 * e]) + fabsl((long double)sn - tw2[2 * e + 1]);
+            if (best_mod < 0.0L || mod < best_mod || (mod == best_mod && dist < best_dist)) {
+              best_mod = mod;
+              best_dist = dist;
+              bc = c;
+              bs = sn;
+            }
+          }
+        tf[2 * e] = bc;
+        tf[2 * e + 1] = bs;
+      }
       ALLOC(P->twd[d], sizeof(float) * 2 * n);
       if (hipMemcpy(P->twd[d], tf.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(P);
