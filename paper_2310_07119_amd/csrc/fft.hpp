@@ -115,11 +115,19 @@ template <class T, bool INV>
 struct Butterfly<T, 3, INV> {
   // X0 = a+b+c; X1,2 = a - (b+c)/2 -+ i (sqrt3/2)(b-c) for the forward sign
   static __device__ __forceinline__ void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
-    const T h = (T)0.86602540378443864676372317075294;
+    // x sqrt3/2; in FP32 with a float-pair constant rounded once (see the
+    // radix-8 butterfly)
+    auto h = [](T x) -> T {
+      if constexpr (sizeof(T) == 4) {
+        return __builtin_fmaf(0.8660254f, x, 1.5543625e-08f * x);
+      } else {
+        return (T)0.86602540378443864676372317075294 * x;
+      }
+    };
     const cx<T> t = b + c;
     const cx<T> m = {a.re - (T)0.5 * t.re, a.im - (T)0.5 * t.im};
     const cx<T> d = b - c;
-    const cx<T> q = INV ? cx<T>{-h * d.im, h * d.re} : cx<T>{h * d.im, -h * d.re};
+    const cx<T> q = INV ? cx<T>{-h(d.im), h(d.re)} : cx<T>{h(d.im), -h(d.re)};
     a = a + t;
     b = m + q;
     c = m - q;
@@ -162,15 +170,26 @@ struct Butterfly<T, 8, INV> {
     cx<T> o0 = v[i0 + step], o1 = v[i0 + 3 * step], o2 = v[i0 + 5 * step], o3 = v[i0 + 7 * step];
     Butterfly<T, 4, INV>::dft4(e0, e1, e2, e3);
     Butterfly<T, 4, INV>::dft4(o0, o1, o2, o3);
-    const T h = (T)0.70710678118654752440084436210485;
+    // x / sqrt2. In FP32 the constant is a float pair (hi + lo = 1/sqrt2 to
+    // about 2^-50) and the product is rounded once; a single float constant is
+    // 1.7e-8 (relative) short and shrinks every transform's output norm by a
+    // fixed fraction, which accumulated to most of the FP32 norm drift over
+    // long runs.
+    auto h = [](T x) -> T {
+      if constexpr (sizeof(T) == 4) {
+        return __builtin_fmaf(0.70710677f, x, 1.21016175e-08f * x);
+      } else {
+        return (T)0.70710678118654752440084436210485 * x;
+      }
+    };
     // W8^1 = (1 -+ i)/sqrt2, W8^2 = -+i, W8^3 = (-1 -+ i)/sqrt2 (forward sign first)
     cx<T> w1o1, w2o2, w3o3;
     if constexpr (!INV) {
-      w1o1 = {h * (o1.re + o1.im), h * (o1.im - o1.re)};
-      w3o3 = {h * (o3.im - o3.re), -h * (o3.re + o3.im)};
+      w1o1 = {h(o1.re + o1.im), h(o1.im - o1.re)};
+      w3o3 = {h(o3.im - o3.re), -h(o3.re + o3.im)};
     } else {
-      w1o1 = {h * (o1.re - o1.im), h * (o1.im + o1.re)};
-      w3o3 = {-h * (o3.re + o3.im), h * (o3.re - o3.im)};
+      w1o1 = {h(o1.re - o1.im), h(o1.im + o1.re)};
+      w3o3 = {-h(o3.re + o3.im), h(o3.re - o3.im)};
     }
     w2o2 = mul_mi<T, INV>(o2);
     v[i0] = e0 + o0;
