@@ -22,6 +22,12 @@ The traffic figure takes two counter runs and a calibration:
       (KiB per dispatch) over the dispatches of the kernel kind, scales them and
       writes a JSON summary together with a digest of the kernel sources, so a
       reader can tell whether the kernels changed since the counters were taken.
+
+  python -m paper_2310_07119_amd.traffic counters --dirs DIR [DIR ...] --out FILE.md
+      per-dispatch SQ counters of the pass kernels of one precision and length
+      (from one or more --pmc runs) with rocprofv3's own derived figures:
+      VALU busy, LDS activity, bank-conflict cycles and conflicts per access,
+      and the FP64 FLOP rate from the instruction counts.
 """
 import argparse
 import csv
