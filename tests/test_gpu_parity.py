@@ -15,6 +15,8 @@ CASES = [
     # (n, n_real, nsteps, dt, hbar, G, m_tot, n_tot)
     ((256,), 64, 40, 1e-4, 1.0, 1.0, 1.0, 1e4),            # 1D workload shape, fewer steps
     ((16,), 3, 25, 1e-3, 0.3, 2.0, 5.0, 50.0),              # 1D tiny, odd ensemble
+    ((96,), 5, 30, 1e-3, 0.5, 1.0, 3.0, 100.0),             # 1D, 3*2^k length (radix-4/2/6 stages)
+    ((1024,), 4, 20, 1e-4, 1.0, 1.0, 1.0, 1e5),             # 1D, longest axis (sixteen points per thread)
     ((64, 32), 5, 12, 2e-4, 1.0, 1.0, 30.0, 1e5),           # 2D, several tiles, odd ensemble
     ((32, 128), 2, 10, 2e-4, 0.5, 3.0, 10.0, 1e5),          # 2D, long y axis
     ((16, 16, 32), 3, 6, 2e-4, 1.0, 1.0, 20.0, 1e6),        # 3D
