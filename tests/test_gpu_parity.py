@@ -167,3 +167,25 @@ def test_2d_mixed_radix_and_long_axes(n, precision, transpose, monkeypatch):
     tol = TOL[precision]
     assert rel(g["psi"], psi) < tol
     assert rel(g["cl"], tw.evolve(prob, cl0, nsteps, dt)) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_classical_limit_infinite_particle_number(precision):
+    """n_tot = infinity (Sec. "Estimating the breaktime": the classical field is
+    the limit of vanishing noise): every sampled realization is the coherent
+    field bit for bit, and after the steps every realization still equals the
+    classical field run alongside, so Q and Var rho vanish to rounding."""
+    n = (64, 32)
+    p = Problem(n=n, hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=float("inf"), n_real=5, precision=precision)
+    psi_cl = inputs.lognormal_field(n, p.box, kcut=8, seed=2)
+    print(f"classical limit {precision}", flush=True)
+    g = gpu_run(p, psi_cl, 9, 10, 2e-4)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64)
+    assert all(np.array_equal(g["psi0"][r], cl0) for r in range(p.n_real))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for r in range(p.n_real):
+        assert rel(g["psi"][r], g["cl"]) < tol, r
+    m = g["mom"]
+    assert abs(m["Q_raw"]) < tol * np.mean(m["norm"])
+    assert np.max(m["var_rho"]) < tol * np.max(m["mean_rho"]) ** 2
+    assert m["nonfinite"] == 0
