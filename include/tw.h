@@ -109,7 +109,10 @@ int tw_sample(tw_plan plan, const void* psi_cl, uint64_t seed, int64_t real_offs
  *   psi           : device, [n_real][N] fields in the plan's precision, in place.
  *   psi_classical : device, [N] one extra field in the plan's precision that is
  *                   evolved alongside (the noise-free classical run), or NULL.
- * nsteps >= 0; dt finite (negative dt runs backwards). */
+ * nsteps >= 0; dt finite (negative dt runs backwards). TW_CHUNK_PAIRS=k in the
+ * environment (read by tw_plan_create) advances k pairs of fields through all
+ * steps before the next k (a cache-residency option; every pair per launch is
+ * the default and was faster at every k measured). */
 int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt,
             void* stream);
 
