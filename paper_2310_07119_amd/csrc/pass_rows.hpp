@@ -87,6 +87,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   // exchanges carry fences that the compiler does not move loads across, so
   // loads placed later would each wait a full memory latency.
   cx<T> va[R], vb[R], zv[R];
+  // FP64 drift+density pass: the wavefront issues its loads at raised
+  // priority (measured 3.7% faster; the same in the kick pass, 4.5% slower)
+  constexpr bool PRIO = MODE == PASS_DRIFT_RHO && sizeof(T) == 8;
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
   constexpr bool LOAD_PSI = MODE == PASS_DRIFT || MODE == PASS_DRIFT_RHO || MODE == PASS_RHO ||
                             MODE == PASS_KICK_DRIFT || MODE == PASS_KIN_SUM || MODE == PASS_POT_SUM;
   constexpr bool LOAD_Z = MODE == PASS_ZFWD || MODE == PASS_ZINV || MODE == PASS_ZPOISSON ||
@@ -99,6 +103,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   }
   TwiddleCache<T, N> tc;
   tc.load(reinterpret_cast<const cx<T>*>(a.twd), t);
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 
   auto drift = [&](cx<T> (&v)[R]) {
     fft_pencil<T, N, false, SW>(v, lds, t, tc);
