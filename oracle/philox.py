@@ -23,8 +23,11 @@ performs the same operations in the same order reproduces it bit for bit:
            coefficient 1/(2k+1) formed by one division);  ln u = e*ln2 + ln m
   angle  : t = 4 u2, q = floor(t), f = t - q; if f > 1/2: f -= 1, q += 1;
            theta = f * (pi/2) in [-pi/4, pi/4]
-  sin    : p = 1; for k = 10..1: p = 1 - (p*theta^2) / ((2k)(2k+1));  sin = theta*p
-  cos    : p = 1; for k = 10..1: p = 1 - (p*theta^2) / ((2k-1)(2k));  cos = p
+  sin    : p = 1; for k = 10..1: p = 1 - (p*theta^2) * r_k;  sin = theta*p,
+           r_k = 1/((2k)(2k+1)) rounded once to double
+  cos    : p = 1; for k = 10..1: p = 1 - (p*theta^2) * c_k;  cos = p,
+           c_k = 1/((2k-1)(2k)) rounded once to double
+           (multiplications by the rounded reciprocals, not divisions)
            rotated by q quarter turns
   z1 = sqrt(-2 ln u1) cos(2 pi u2),  z2 = sqrt(-2 ln u1) sin(2 pi u2)
 """

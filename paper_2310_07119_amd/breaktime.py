@@ -16,9 +16,15 @@ paper does on it, on the host, over a few hundred scalars:
 * spectra over time: per-mode occupations <|a_k|^2> averaged over shells of
   |k| (the mode_occ output of tw_moments).
 
-Q_s is the normal-ordered estimator (Q_sym of tw_moments: the Weyl half
-quantum per mode removed), which is zero in expectation for the coherent
-initial state, as Eq. (Q) requires.
+The sampled ensemble only estimates the initial Wigner function, so the
+simulated Q at t = 0 is not exactly zero; the paper therefore subtracts the
+sampled initial value and analyses Q_s(t) - Q_s(0) (Sec. "Estimating the
+breaktime"). `record` returns that series as Q_minus_Q0 (Q_raw minus its value
+at the first output, which `record` takes at the start of the run). Q_sym of
+tw_moments (Q_raw with the Weyl half quantum per cell mode, N / (2 n_tot),
+removed) is not a substitute at t = 0: with the plug-in estimator
+E Q_raw(0) = (1 - 1/N_s) N / (2 n_tot), so E Q_sym(0) = -N / (2 n_tot N_s),
+a bias that shrinks only as 1/N_s.
 """
 from __future__ import annotations
 
@@ -118,8 +124,9 @@ def shell_spectrum(mode_occ, box):
 def record(plan, psi, psi_classical, nsteps: int, dt: float, every: int, modes: bool = False):
     """Advance the ensemble `nsteps` steps of size dt on the GPU, taking the
     moments every `every` steps (and at t = 0). Returns a dict of host arrays:
-    t, Q_raw, Q_sym, dev_rho_L1, dev_psi_L2 (and mode_occ, one field-shaped
-    array per output, if modes)."""
+    t, Q_raw, Q_sym, Q_minus_Q0 (Q_raw minus its sampled value at the first
+    output: the series the paper fits), dev_rho_L1, dev_psi_L2 (and mode_occ,
+    one field-shaped array per output, if modes)."""
     if every <= 0 or nsteps < 0:
         raise ValueError("every must be positive and nsteps non-negative")
     keys = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2")
@@ -139,4 +146,6 @@ def record(plan, psi, psi_classical, nsteps: int, dt: float, every: int, modes: 
         k = min(every, nsteps - done)
         plan.step(psi, k, dt, psi_classical)
         done += k
-    return {k: (np.asarray(v) if k != "mode_occ" else v) for k, v in out.items()}
+    res = {k: (np.asarray(v) if k != "mode_occ" else v) for k, v in out.items()}
+    res["Q_minus_Q0"] = res["Q_raw"] - res["Q_raw"][0]
+    return res

@@ -89,3 +89,29 @@ def test_shell_spectrum_bookkeeping():
     k2, mean2, _ = bt.shell_spectrum(shell, box)
     assert np.allclose(mean2, k2 / dk)
     assert k[0] == 0.0 and mean2[0] == 0.0
+
+
+class _StubPlan:
+    """Host stand-in for a plan: Q_raw grows by a known amount per step."""
+
+    def __init__(self, q0):
+        self.q = q0
+        self.steps = []
+
+    def moments(self, psi, psi_cl, energy=False, per_cell=False, modes=False):
+        return {"Q_raw": self.q, "Q_sym": self.q - 0.5, "dev_rho_L1": 0.0, "dev_psi_L2": 0.0}
+
+    def step(self, psi, k, dt, psi_cl):
+        self.steps.append(k)
+        self.q += 0.25 * k
+
+
+def test_record_subtracts_the_sampled_initial_q():
+    """Sec. 'Estimating the breaktime': the sampled Q(0) is not zero and is
+    subtracted; outputs every `every` steps, the last one at nsteps."""
+    plan = _StubPlan(q0=3.0)
+    rec = bt.record(plan, None, None, nsteps=7, dt=0.1, every=3)
+    assert plan.steps == [3, 3, 1]
+    assert np.allclose(rec["t"], [0.0, 0.3, 0.6, 0.7])
+    assert np.array_equal(rec["Q_raw"], [3.0, 3.75, 4.5, 4.75])
+    assert np.array_equal(rec["Q_minus_Q0"], [0.0, 0.75, 1.5, 1.75])

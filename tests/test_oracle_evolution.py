@@ -285,3 +285,92 @@ def test_cic_interpolation_is_exact_for_linear_fields():
     got = tw.interpolate(prob, F, pos)
     for i, (px, py) in enumerate([(0.3, 0.1), (1.6, 0.7), (0.3, 0.1)]):
         assert abs(got[0, i] - (1.0 + 2.0 * px - 3.0 * py + 0.5 * px * py)) < 1e-14
+
+
+def _cosine_background(n, box, axis, mode, eps, m_tot):
+    """Real field psi' = sqrt((1 + eps cos k0 u) / volume), u the coordinate
+    along `axis`, k0 = 2 pi mode / L_axis: density rho = rho_bar (1 + eps cos k0 u)."""
+    grid = tw.Grid(n, box)
+    coords = np.meshgrid(*[np.arange(m) * L / m for m, L in zip(reversed(n), reversed(box))], indexing="ij")
+    u = coords[grid.dim - 1 - axis]
+    k0 = 2 * np.pi * mode / box[axis]
+    psi = np.sqrt((1 + eps * np.cos(k0 * u)) / grid.volume).astype(complex)
+    return grid, psi, k0, m_tot / grid.volume
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_tracer_push_is_the_cosine_density_force(axis):
+    """One step of a particle at rest in the field of rho = rho_bar (1 + eps cos k0 u):
+    Poisson gives V = -4 pi G rho_bar eps cos(k0 u) / k0^2, so the kick is
+    dv_u = -dt dV/du = -dt 4 pi G rho_bar eps sin(k0 u0) / k0 and the other
+    component stays 0 (Sec. "Modeling decoherence": dv/dt = -grad V). The
+    field's own motion over dt/2 and the fourth-order difference change this
+    by O(dt^2) and O((k0 du)^4); a flipped sign, a wrong factor or a swapped
+    axis miss it by far more than the tolerance."""
+    n, box = (32, 48), (1.5, 2.0)
+    G, m_tot, eps, dt = 3.0, 2.0, 0.3, 1e-4
+    grid, psi, k0, rho_bar = _cosine_background(n, box, axis, 1, eps, m_tot)
+    prob = tw.Problem(grid, hbar_m=0.5, G=G, m_tot=m_tot)
+    du = box[axis] / n[axis]
+    # on grid points (interpolation exact) and between them (linear weights)
+    starts = [(5 * box[0] / n[0], 7 * box[1] / n[1]), (0.37 * box[0], 0.61 * box[1])]
+    tr = np.zeros((1, len(starts), 4))
+    tr[0, :, :2] = starts
+    _, got = tw.step_tracers(prob, psi[None], tr, dt)
+    amp = 4 * np.pi * G * rho_bar * eps / k0
+    other = 1 - axis
+    for i, (tol, p) in enumerate([(1e-4, starts[0]), (5e-3, starts[1])]):
+        expect = -dt * amp * np.sin(k0 * p[axis])
+        assert abs(got[0, i, 2 + axis] - expect) < tol * abs(expect), (i, got[0, i], expect)
+        assert abs(got[0, i, 2 + other]) < 1e-12 * abs(expect)
+        # positions: the second half drift moves by v dt / 2
+        assert abs(got[0, i, axis] - (p[axis] + 0.5 * dt * got[0, i, 2 + axis])) < 1e-15
+        assert got[0, i, other] == p[other]
+
+
+def test_energy_of_a_plane_wave_is_kinetic_only():
+    """psi' = exp(i k.x) / sqrt(volume): uniform density, so V = 0 whatever G,
+    and E = M_tot hbar^2 |k|^2 / 2 exactly (Eq. (mft_normed) energy)."""
+    n, box = (16, 24), (1.5, 2.0)
+    grid = tw.Grid(n, box)
+    prob = tw.Problem(grid, hbar_m=0.7, G=5.0, m_tot=3.0)
+    y, x = np.meshgrid(np.arange(24) * 2.0 / 24, np.arange(16) * 1.5 / 16, indexing="ij")
+    kx, ky = 2 * np.pi * 3 / 1.5, 2 * np.pi * (-2) / 2.0
+    psi = np.exp(1j * (kx * x + ky * y)) / np.sqrt(grid.volume)
+    expect = 3.0 * 0.7 ** 2 * (kx * kx + ky * ky) / 2
+    assert abs(tw.energy(prob, psi[None])[0] - expect) < 1e-13 * expect
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_energy_of_a_cosine_density_closed_form(dim):
+    """psi' = sqrt((1 + eps cos k0 u) / volume):
+    int |grad psi'|^2 = k0^2 (1 - sqrt(1 - eps^2)) / 4 (from the integral of
+    sin^2/(1 + eps cos) over a period), and (1/2) int V |psi'|^2 =
+    -pi G rho_bar eps^2 / k0^2 with the closed-form potential, so
+    E = M_tot [hbar^2 k0^2 (1 - sqrt(1 - eps^2)) / 8 - pi G rho_bar eps^2 / k0^2].
+    A dropped or doubled M_tot, a missing cell volume or a wrong weight between
+    the two terms all change E by far more than the tolerance."""
+    n, box = ((64,), (2.0,)) if dim == 1 else ((16, 48), (1.5, 2.0))
+    axis = dim - 1
+    hbar, G, m_tot, eps = 0.8, 1.0, 3.0, 0.5
+    grid, psi, k0, rho_bar = _cosine_background(n, box, axis, 1, eps, m_tot)
+    prob = tw.Problem(grid, hbar_m=hbar, G=G, m_tot=m_tot)
+    kin = hbar ** 2 * k0 ** 2 * (1 - np.sqrt(1 - eps ** 2)) / 8
+    pot = -np.pi * G * rho_bar * eps ** 2 / k0 ** 2
+    expect = m_tot * (kin + pot)
+    assert abs(kin) > 0.1 * abs(pot) and abs(pot) > 0.1 * abs(kin)   # both terms matter
+    got = tw.energy(prob, psi[None])[0]
+    assert abs(got - expect) < 1e-12 * abs(m_tot * kin), (got, expect)
+
+
+def test_tracer_spread_brute_force():
+    """Plug-in variance over realizations, written out for three realizations
+    and one particle (the extra classical slot beyond n_real is ignored)."""
+    t = np.array([[[0.0, 1.0, 2.0, -1.0]], [[0.3, 1.0, 2.5, -1.0]], [[0.9, 0.7, 1.0, 0.5]],
+                  [[50.0, 50.0, 50.0, 50.0]]])
+    got = tw.tracer_spread(t, 3)
+    for d in range(4):
+        vals = [t[0, 0, d], t[1, 0, d], t[2, 0, d]]
+        m = (vals[0] + vals[1] + vals[2]) / 3
+        var = ((vals[0] - m) ** 2 + (vals[1] - m) ** 2 + (vals[2] - m) ** 2) / 3
+        assert abs(got[0, d] - var) < 1e-15
