@@ -57,10 +57,70 @@ def pass_bytes(kind, elem, ncell, nfield, n_real):
         "pass_rho": f + z,
         "pass_kin_sum": f,
         "pass_pot_sum": z + f,
+        "pass_slab_drift": 2 * f,
+        "pass_slab_drift_rho": 2 * f + z,
+        "pass_slab_poisson": 2 * z,
+        "pass_slab_kick_drift": z + 2 * f,
         "step1d_resident": 2 * f,
         "sample": 16 * ncell + elem * ncell * n_real,
         "moments": elem * ncell * nfield + 40 * ncell,
     }.get(kind)
+
+
+def alg_bytes_per_cell_step(precision):
+    """Algorithmic HBM bytes of the method per realization*cell*step: the state
+    read once and written once (complex128: 32 B; complex64: 16 B)."""
+    return 32 if precision == "fp64" else 16
+
+
+# Kernel kinds that make up the steps (tw_step): everything else in a timed run
+# (sampling, moment reductions, energy passes) happens once per run.
+STEP_KINDS = ("pass_drift", "pass_drift_rho", "pass_zfwd", "pass_zpoisson", "pass_zinv", "pass_kick_drift",
+              "pass_slab_drift", "pass_slab_drift_rho", "pass_slab_poisson", "pass_slab_kick_drift", "step1d_resident",
+              "field_mean", "tables")
+
+
+def roofline_of(prof, precision, elem, ncell, nfield, n_real, steps_timed, step_prof=None, ms_per_step=None):
+    """Roofline object of a timed run.
+
+    achieved: the algorithmic bytes one launch of the dominant kernel stands
+    for (alg_bytes_per_cell_step x the nfield*ncell cells of one step, which
+    is what one launch of a step pass covers) over that kernel's average
+    launch duration; frac = achieved / peak. The kernel's own compulsory bytes
+    (its inputs read once, outputs written once) are reported beside it
+    (kernel_gbs, kernel_frac), and, from a profiled call of the steps alone
+    (step_prof), the bytes all step passes move per realization*cell*step and
+    their ratio to the algorithmic figure (the cost of the pass count)."""
+    kind, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_s = total_ms / launches / 1e3
+    alg = alg_bytes_per_cell_step(precision) * nfield * ncell
+    own = pass_bytes(kind, elem, ncell, nfield, n_real)
+    achieved = alg / avg_s / 1e9
+    r = {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+         "alg_bytes_per_launch": alg, "alg_bytes_per_cell_step": alg_bytes_per_cell_step(precision),
+         "avg_launch_ms": avg_s * 1e3, "launches": launches,
+         "kernel_bytes_per_launch": own,
+         "kernel_gbs": (own / avg_s / 1e9) if own else None,
+         "kernel_frac": (own / avg_s / 1e9 / HBM_PEAK_GBS) if own else None}
+    if ms_per_step:
+        r["step_frac"] = alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if step_prof:
+        steps = step_prof["steps"]
+        tot_b, tot_ms = 0.0, 0.0
+        for k, (nl, ms) in step_prof["prof"].items():
+            if k not in STEP_KINDS:
+                continue
+            tot_ms += ms
+            b = pass_bytes(k, elem, ncell, nfield, n_real)
+            if b:
+                tot_b += nl * b
+        per_cs = tot_b / (steps * nfield * ncell)
+        r["step_kernel_ms"] = tot_ms / steps
+        r["step_kernels_frac"] = alg / (tot_ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS
+        r["pass_bytes_per_cell_step"] = per_cs
+        r["pass_bytes_ratio"] = per_cs / alg_bytes_per_cell_step(precision)
+    return r
 
 
 def measured_traffic(kind, precision, workload):
@@ -131,26 +191,25 @@ def run_gpu(wl, precision, steps, warmup, seed=20231007):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = plan.profile()
-    plan.set_profiling(False)
     elapsed = t1 - t0
+    # the steps alone, profiled once more outside the timed region: bytes and
+    # kernel time per step without sampling and moments
+    plan.step(psi, steps, dt, clt)
+    torch.cuda.synchronize()
+    step_prof = {"steps": steps, "prof": plan.profile()}
+    plan.set_profiling(False)
     work = p.n_real * p.ncell * steps
     res = dict(value=work / elapsed, ms_per_step=1e3 * elapsed / steps, elapsed_s=elapsed, prof=prof,
                mom={k: (v.cpu() if torch.is_tensor(v) else v) for k, v in mom.items()},
                problem=p)
-    # dominant kernel
     elem = 16 if precision == "fp64" else 8
     nfield = p.n_real + 1
-    best = max(prof.items(), key=lambda kv: kv[1][1])
-    kind, (launches, total_ms) = best
-    avg_s = total_ms / launches / 1e3
-    nbytes = pass_bytes(kind, elem, p.ncell, nfield, p.n_real)
-    achieved = nbytes / avg_s / 1e9 if nbytes else None
-    traffic = measured_traffic(kind, precision, wl["name"])
-    res["roofline"] = {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                       "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3, "launches": launches,
-                       # compulsory bytes / bytes the counters saw move (1 = no wasted traffic)
-                       "pass_efficiency": (nbytes / traffic) if (nbytes and traffic) else None}
+    rl = roofline_of(prof, precision, elem, p.ncell, nfield, p.n_real, steps, step_prof, res["ms_per_step"])
+    traffic = measured_traffic(rl["kernel"], precision, wl["name"])
+    rl["traffic"] = traffic
+    # compulsory bytes of the kernel / bytes the counters saw it move (1 = no wasted traffic)
+    rl["pass_efficiency"] = (rl["kernel_bytes_per_launch"] / traffic) if (rl["kernel_bytes_per_launch"] and traffic) else None
+    res["roofline"] = rl
     res["kernel_ms"] = {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     res["strided_variant"] = variant
     plan.close()
@@ -357,7 +416,30 @@ def run_batched(steps, warmup, seed=7):
         pl.step(x, steps, dt)
     torch.cuda.synchronize()
     el1 = time.perf_counter() - t0
+    # error against the plain FP64 path: the same draws (the FP32 state is the
+    # FP64 draw rounded), advanced by the batch in FP32 and by one FP64 plan
+    # per class, moments compared normwise per class
+    err = []
+    for c, p in enumerate(probs):
+        cl = torch.from_numpy(inputs.soliton_3d(p.n, p.box, core=0.1)).cuda()
+        psis[c] = batch.plans[c].sample(cl, seed)
+    batch.step(psis, steps, dt)
+    p64s = [Problem(n=p.n, box=p.box, hbar_m=p.hbar_m, G=p.G, m_tot=p.m_tot, n_tot=p.n_tot, n_real=p.n_real,
+                    precision="fp64") for p in probs]
+    for c, (p, p64) in enumerate(zip(probs, p64s)):
+        m32 = batch.plans[c].moments(psis[c], energy=True)
+        plan64 = Plan(p64)
+        cl = torch.from_numpy(inputs.soliton_3d(p.n, p.box, core=0.1)).cuda()
+        x64 = plan64.sample(cl, seed)
+        plan64.step(x64, steps, dt)
+        m64 = plan64.moments(x64, energy=True)
+        err.append({"class": list(p.n), **{k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm",
+                                                                              "energy")}})
+        plan64.close()
+        del x64
+    torch.cuda.empty_cache()
     out = {"workload": "3d_batched_soliton", "classes": [list(p.n) for p in probs],
+           "err_vs_fp64": err,
            "n_real_per_class": wl["n_real"], "precision": "fp32", "steps": steps,
            "value": work / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
            "unbatched_value": work / el1, "speedup_vs_unbatched": el1 / el, "strided_pass_variant": variant,
@@ -552,6 +634,7 @@ def main():
         out["fp32_split"] = {
             "value": r32["value"], "ms_per_step": r32["ms_per_step"], "speedup": r32["value"] / main_run["value"],
             "roofline_frac": r32["roofline"]["frac"], "kernel": r32["roofline"]["kernel"],
+            "step_frac": r32["roofline"].get("step_frac"), "pass_bytes_ratio": r32["roofline"].get("pass_bytes_ratio"),
             "strided_pass_variant": r32["strided_variant"],
             "err_vs_fp64": {k: rel(m32[k], m64[k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")},
         }

@@ -1,7 +1,8 @@
 """FNO surrogate on the GPU (BF16 matrix cores, FP32 accumulate) against the
-FP64 oracle with the same BF16 operand rounding: forward within 5e-3 and
-every parameter gradient within 2e-2 normwise (accumulation in FP32 vs FP64 and
-GELU in FP32); MSE and Adam kernels against their oracles."""
+FP64 oracle with the same BF16 operand rounding: forward within 1e-3 and
+every parameter gradient within 1e-2 normwise (accumulation in FP32 vs FP64,
+GELU in FP32, and the BF16 roundings an FP32 intermediate can tip to the
+neighbouring value); MSE and Adam kernels against their oracles."""
 import numpy as np
 import pytest
 import torch
@@ -45,11 +46,11 @@ def test_forward_backward_vs_oracle(name, batch):
     torch.cuda.synchronize()
     params = net.params.cpu().numpy().astype(np.float64)
     yo = fo.forward(cfg, params, x.astype(np.float64))
-    assert rel(y.cpu().numpy(), yo) < 5e-3
+    assert rel(y.cpu().numpy(), yo) < 1e-3
     go = fo.backward(cfg, params, x.astype(np.float64), dy.astype(np.float64))
     gg = fo.unflatten(cfg, g.cpu().numpy())
     for key, _ in cfg.shapes():
-        assert rel(gg[key], go[key]) < 2e-2, key
+        assert rel(gg[key], go[key]) < 1e-2, key
     net.close()
 
 

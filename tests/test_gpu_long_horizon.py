@@ -52,20 +52,20 @@ def test_full_horizon_norm_and_energy_order():
     torch.cuda.empty_cache()
 
 
-def test_3d_fp32_split_full_run_against_fp64():
-    """The 3D 128^3 workload (64 realizations, 2000 steps of 1e-4) in the FP32
-    split form against the same run in FP64: per-cell moments, norms and
-    energies agree normwise to 2e-3 at the end (measured at most 1.7e-4, for
-    Var rho), and the FP64 norms are conserved to 1e-10."""
-    w = inputs.WORKLOADS["3d_n128_grf"]
-    cl = torch.from_numpy(inputs.initial_field("3d_n128_grf")).cuda()
+def _fp32_against_fp64(name, seed):
+    """Run workload `name` over its full horizon in the FP32 split form and in
+    FP64 from the same draws (the FP32 state is the FP64 draw rounded); returns
+    the normwise error of every moment of the FP32 run against the FP64 run."""
+    w = inputs.WORKLOADS[name]
+    cl = torch.from_numpy(inputs.initial_field(name)).cuda()
     out = {}
     for prec in ("fp32", "fp64"):
-        print(f"3d full run: {prec}", flush=True)
+        print(f"{name} full run ({w['nsteps']} steps): {prec}", flush=True)
         p = Problem(n=w["n"], box=w["box"], hbar_m=w["hbar_m"], G=w["G"], m_tot=w["m_tot"], n_tot=w["n_tot"],
                     n_real=w["n_real"], precision=prec)
         plan = Plan(p)
-        psi = plan.sample(cl, 9)
+        plan.autotune()
+        psi = plan.sample(cl, seed)
         clt = cl.to(p.cdtype).clone()
         n0 = plan.moments(psi, clt, energy=False)["norm"].cpu().numpy()
         plan.step(psi, w["nsteps"], w["dt"], clt)
@@ -79,9 +79,39 @@ def test_3d_fp32_split_full_run_against_fp64():
         torch.cuda.empty_cache()
 
     def rel(a, b):
-        return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
-    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
-        assert rel(out["fp32"][k], out["fp64"][k]) < 2e-3, k
+    err = {k: rel(out["fp32"][k], out["fp64"][k]) for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy")}
     for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2", "energy_classical"):
-        assert abs(out["fp32"][k] - out["fp64"][k]) < 2e-3 * abs(out["fp64"][k]), k
+        err[k] = abs(out["fp32"][k] - out["fp64"][k]) / abs(out["fp64"][k])
+    print(f"{name} FP32 against FP64 after {w['nsteps']} steps: " +
+          ", ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+    return err
+
+
+# Errors of the FP32 split form against FP64 at the end of each full run
+# (normwise over the whole output array; scalars relative). 2D, measured on
+# MI355X: mean_psi 1.08e-4, mean_rho 1.41e-4, var_rho 1.47e-4, norm 9.96e-5,
+# energy 1.0e-6, Q_raw 5.5e-7, dev_rho_L1 5.2e-7, dev_psi_L2 2.0e-7, classical
+# energy 1.12e-4: the FP32 fields lose 2e-8 of their norm per step, the same
+# for every field, which the realizations' energies (dominated by the
+# vacuum noise at high k) and Q barely see. The bounds are about twice the
+# measured values. 3D: every moment within the 1e-4 bar.
+FP32_FULL_RUN_BOUNDS = {
+    "2d_n512_pair": {"mean_psi": 2.2e-4, "mean_rho": 2.8e-4, "var_rho": 3e-4, "norm": 2e-4, "energy": 2e-6,
+                     "Q_raw": 1.1e-6, "dev_rho_L1": 1.1e-6, "dev_psi_L2": 4e-7, "energy_classical": 2.2e-4},
+    "3d_n128_grf": {"mean_psi": 1e-4, "mean_rho": 1e-4, "var_rho": 1e-4, "norm": 1e-4, "energy": 1e-4,
+                    "Q_raw": 1e-4, "dev_rho_L1": 1e-4, "dev_psi_L2": 1e-4, "energy_classical": 1e-4},
+}
+
+
+@pytest.mark.parametrize("name", ["2d_n512_pair", "3d_n128_grf"])
+def test_fp32_split_full_run_against_fp64(name):
+    """The 2D benchmark workload (512^2, 256 realizations, 5000 steps) and the
+    3D 128^3 workload (64 realizations, 2000 steps) in the FP32 split form
+    against the same runs in FP64: every moment within its stated bound at the
+    end of the full horizon; the FP64 norms are conserved to 1e-10."""
+    err = _fp32_against_fp64(name, 9)
+    bounds = FP32_FULL_RUN_BOUNDS[name]
+    bad = {k: v for k, v in err.items() if not v < bounds[k]}
+    assert not bad, bad

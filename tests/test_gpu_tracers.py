@@ -65,7 +65,9 @@ def test_tracers_vs_oracle(case, precision, transpose, monkeypatch):
     moved = np.abs(ref_tr[:, :, D:] - tr0[:, :, D:]).max()
     assert moved > 1e-3, "gravity should change the velocities"
     assert rel(got[:, :, :D], ref_tr[:, :, :D]) < tol
-    assert rel(got[:, :, D:], ref_tr[:, :, D:]) < tol * 10
+    assert rel(got[:, :, D:], ref_tr[:, :, D:]) < tol
+    # the velocity change alone (what gravity did) at the same bar
+    assert rel(got[:, :, D:] - tr0[:, :, D:], ref_tr[:, :, D:] - tr0[:, :, D:]) < tol
     spread = plan.tracer_spread(tr).cpu().numpy()
     assert rel(spread, tw.tracer_spread(got, nr)) < 1e-12
     plan.close()

@@ -93,3 +93,30 @@ def test_bench_traffic_needs_matching_kernel_sources(monkeypatch):
     monkeypatch.setattr(traffic, "source_digest", lambda: "changed")
     assert bench.measured_traffic("pass_kick_drift", "fp64", "2d_n512_pair") is None
     assert bench.measured_traffic("pass_kick_drift", "fp64", "no_such_workload") is None
+
+
+def test_bench_roofline_uses_algorithmic_bytes_per_cell_step():
+    """The roofline's achieved rate is 32 B (FP64) per realization*cell*step
+    times the cells one launch covers, over the dominant kernel's average
+    launch; the step figures add up every step pass from a steps-only profile."""
+    import bench
+    ncell, nfield, n_real = 512 * 512, 257, 256
+    prof = {"pass_kick_drift": (50, 50 * 0.5), "pass_drift_rho": (51, 51 * 0.45), "pass_zpoisson": (51, 51 * 0.25),
+            "sample": (1, 0.9)}
+    step_prof = {"steps": 50, "prof": {"pass_kick_drift": (50, 25.0), "pass_drift_rho": (50, 22.5),
+                                       "pass_zpoisson": (50, 12.5), "pass_drift": (1, 0.4)}}
+    r = bench.roofline_of(prof, "fp64", 16, ncell, nfield, n_real, 50, step_prof, ms_per_step=1.5)
+    alg = 32 * nfield * ncell
+    assert r["kernel"] == "pass_kick_drift" and r["alg_bytes_per_launch"] == alg
+    assert abs(r["achieved"] - alg / 0.5e-3 / 1e9) < 1e-9 * r["achieved"]
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15
+    assert abs(r["step_frac"] - alg / 1.5e-3 / 1e9 / 8000.0) < 1e-12
+    assert abs(r["step_kernel_ms"] - (25.0 + 22.5 + 12.5 + 0.4) / 50) < 1e-12
+    # 2D FP64 schedule: drift+rho 2f + z, Poisson 2z, kick 2f + z per step (f: every field once, z: the
+    # pair scratch once, 129 pairs for 257 fields: about 96 B per field*cell), plus one opening drift
+    f, z = 16 * ncell * nfield, 16 * ncell * 129
+    per_cs = (50 * (4 * f + 4 * z) + 2 * f) / (50 * nfield * ncell)
+    assert 96.6 < per_cs < 96.8
+    assert abs(r["pass_bytes_per_cell_step"] - per_cs) < 1e-9
+    assert abs(r["pass_bytes_ratio"] - per_cs / 32) < 1e-9
+    assert bench.alg_bytes_per_cell_step("fp32") == 16
