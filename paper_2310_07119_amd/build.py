@@ -23,7 +23,7 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
 # The sampler must not contract a*b+c into fma: its draws are defined as a
 # fixed sequence of correctly rounded operations.
 PER_FILE = {"kernels_sample.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "tune.hip", "kernels_step.hip", "kernels_cols.hip", "kernels_batch.hip",
+SOURCES = ["api.hip", "tune.hip", "kernels_step.hip", "kernels_cols.hip", "kernels_slab.hip", "kernels_batch.hip",
            "kernels_sample.hip", "kernels_moments.hip", "kernels_tracers.hip", "kernels_fno.hip", "fno.hip"]
 
 

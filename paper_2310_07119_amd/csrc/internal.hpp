@@ -40,6 +40,16 @@ struct PassArgs {
   const double* kick_dev;  // PASS_KICK_DRIFT: kick factor dt/hbar read from device memory (overrides kick)
   double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V|, kVmaxBuckets slots (atomic max on the bits)
   int32_t store_v;         // PASS_KICK_DRIFT: write the real-space potentials V_A + i V_B back into the pair scratch
+  const void* phase2;      // plane passes (D = 3): drift factors along y (phase: along x)
+};
+
+// Passes over whole xy-planes of a D = 3 grid held in LDS (kernels_slab.hip).
+enum SlabMode : int {
+  SLAB_DRIFT = 0,       // psi <- drift along x, then along y
+  SLAB_DRIFT_RHO = 1,   // drift x, y; z <- FFT_xy(rho_A - mean_A + i (rho_B - mean_B))
+  SLAB_POISSON = 2,     // z <- IFFT_xy(G(k) FFT_xy z)   (z already transformed along z)
+  SLAB_KICK_DRIFT = 3,  // V_A + i V_B <- IFFT_xy z; psi <- kick; drift x, y
+  SLAB_NMODES = 4
 };
 
 enum PassMode : int {
@@ -86,6 +96,9 @@ struct Plan {
   int split_streams;     // tw_step runs two halves of the pairs on two streams
   hipStream_t side;      // the second stream (created on first use, default priority)
   hipEvent_t ev_fork, ev_join;
+  int32_t slab3d;        // D = 3 steps use the xy-plane passes (3 HBM passes per step instead of 6)
+  int32_t slab_ok;       // the plane kernels exist for this grid and fit the device's LDS
+  int32_t slab_tuned;    // slab3d came from a measurement, the tuning cache or TW_SLAB
   int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
   int32_t tuned;         // cols_variant came from a measurement or the tuning cache
   // kernel timing (tw_plan_set_profiling)
@@ -101,12 +114,22 @@ enum KernelKind : int {
   KIND_MEAN = 13,
   KIND_ENERGY = 14,
   KIND_MODES = 15,  // mode occupations and the amplitude/phase spread
-  KIND_COUNT = 16
+  KIND_SLAB = 16,   // KIND_SLAB + SlabMode: the xy-plane passes
+  KIND_COUNT = KIND_SLAB + SLAB_NMODES
 };
+
+// Opt kernel `kern` into `bytes` of dynamic LDS (needed above 64 KiB) before
+// its first launch with that size; remembered per kernel, so every
+// instantiation and every pass mode is set up once (thread-safe).
+hipError_t ensure_dynamic_lds(const void* kern, size_t bytes);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_pass(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs_or_fields);
 hipError_t launch_pass_cols(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs);
+// xy-plane pass over n[2] planes of pairs [pair0, pair0 + npairs); needs n[0] == n[1]
+hipError_t launch_slab(const Plan& P, int mode, const PassArgs& a, hipStream_t s, int npairs);
+// LDS bytes of the plane kernels for an n x n plane, 0 if none is compiled for n
+size_t slab_lds_bytes(int n, bool fp32);
 int cols_pencils_per_group(int n, bool fp32);
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* phase_half, const void* phase_full, double kick, hipStream_t s);
@@ -136,6 +159,19 @@ hipError_t launch_decoherence(const Plan& P, const void* psi, double* var_amp, d
 hipError_t launch_mode_occ(const Plan& P, int64_t nslots, int accumulate, double* occ, hipStream_t s);
 hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
                           const double* energy_dev, hipStream_t s);
+// The moment reductions of launch_moments on an explicit geometry and partial-sum
+// buffer of moments_partial_doubles(n_real, ncell) doubles.
+struct MomGeom {
+  int64_t n_real, ncell;
+  double m_tot, dV, n_tot;
+  bool fp32;
+};
+int64_t moments_partial_doubles(int64_t n_real, int64_t ncell);
+hipError_t launch_moments_geom(const MomGeom& G, double* partial, const void* psi, const void* psi_cl,
+                               const tw_moments_out* out, const double* energy_dev, hipStream_t s);
+// Error reporting shared by the entry points: stores the message returned by
+// tw_last_error and returns `code`.
+int report_error(int code, const char* fmt, ...);
 
 // Grouped launch over the size classes of a batch (kernels_batch.hip).
 constexpr int kMaxClasses = 4;

@@ -120,8 +120,7 @@ static hipError_t launch_grouped_tk(int mode, GroupArgs& g, hipStream_t s) {
   if (start == 0) return hipSuccess;
   auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(start), dim3(256), lds, s, g);

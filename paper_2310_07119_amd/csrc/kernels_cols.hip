@@ -20,13 +20,8 @@ static hipError_t launch_cols_tn(int mode, const PassArgs& a, hipStream_t s, int
   dim3 block(Cfg::THREADS);
   auto go = [&](auto kern) -> hipError_t {
     if constexpr (Cfg::LDS > 64 * 1024) {
-      static bool attr_set = false;  // per instantiation, once per process
-      if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::LDS);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-      }
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), Cfg::LDS);
+      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, grid, block, Cfg::LDS, s, a);
     return hipGetLastError();

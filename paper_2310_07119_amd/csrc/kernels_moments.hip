@@ -144,40 +144,56 @@ __global__ void __launch_bounds__(256) scalars_kernel(const double* __restrict__
   }
 }
 
-hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
-                          const double* energy_dev, hipStream_t s) {
-  const int64_t nwaves = (P.ncell + 63) / 64;
+int64_t moments_partial_doubles(int64_t n_real, int64_t ncell) {
+  const int64_t nwaves = (ncell + 63) / 64;
+  return n_real * nwaves + 3 * nwaves + n_real + 3;
+}
+
+// Every slot of `partial` that a later kernel reads is written first in the
+// same call (one per wavefront of cells and realization, then the row sums),
+// so the buffer needs no clearing between calls.
+hipError_t launch_moments_geom(const MomGeom& G, double* partial, const void* psi, const void* psi_cl,
+                               const tw_moments_out* out, const double* energy_dev, hipStream_t s) {
+  const int64_t nwaves = (G.ncell + 63) / 64;
   MomArgs a;
   a.psi = psi;
   a.psi_cl = psi_cl;
-  a.n_real = P.p.n_real;
-  a.ncell = P.ncell;
-  a.m_tot = P.p.m_tot;
-  a.dV = P.dV;
+  a.n_real = G.n_real;
+  a.ncell = G.ncell;
+  a.m_tot = G.m_tot;
+  a.dV = G.dV;
   a.mean_psi = reinterpret_cast<cx<double>*>(out->mean_psi);
   a.mean_abs2 = out->mean_abs2;
   a.mean_rho = out->mean_rho;
   a.var_rho = out->var_rho;
-  a.wave_norm = P.partial;
-  a.wave_q = P.partial + P.p.n_real * nwaves;
+  a.wave_norm = partial;
+  a.wave_q = partial + G.n_real * nwaves;
   a.nwaves = nwaves;
   double* norms = a.wave_q + 3 * nwaves;  // [n_real]
-  double* qsum = norms + P.p.n_real;      // [3]
-  dim3 grid((unsigned)((P.ncell + 255) / 256));
-  if (P.fp32) hipLaunchKernelGGL(moments_cell_kernel<float>, grid, dim3(256), 0, s, a);
+  double* qsum = norms + G.n_real;        // [3]
+  dim3 grid((unsigned)((G.ncell + 255) / 256));
+  if (G.fp32) hipLaunchKernelGGL(moments_cell_kernel<float>, grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(moments_cell_kernel<double>, grid, dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(row_sum_kernel, dim3((unsigned)P.p.n_real), dim3(256), 0, s, a.wave_norm, nwaves, P.dV, norms);
+  hipLaunchKernelGGL(row_sum_kernel, dim3((unsigned)G.n_real), dim3(256), 0, s, a.wave_norm, nwaves, G.dV, norms);
   hipLaunchKernelGGL(row_sum_kernel, dim3(3), dim3(256), 0, s, a.wave_q, nwaves, 1.0, qsum);
-  if (out->norm)
-    hipMemcpyAsync(out->norm, norms, sizeof(double) * P.p.n_real, hipMemcpyDeviceToDevice, s);
+  if (out->norm) {
+    e = hipMemcpyAsync(out->norm, norms, sizeof(double) * G.n_real, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   if (out->scalars) {
-    const double vacuum = (double)P.ncell / (2.0 * P.p.n_tot);
-    hipLaunchKernelGGL(scalars_kernel, dim3(1), dim3(256), 0, s, qsum, norms, energy_dev, (int64_t)P.p.n_real, vacuum,
+    const double vacuum = (double)G.ncell / (2.0 * G.n_tot);
+    hipLaunchKernelGGL(scalars_kernel, dim3(1), dim3(256), 0, s, qsum, norms, energy_dev, G.n_real, vacuum,
                        psi_cl ? 1 : 0, energy_dev ? 1 : 0, out->scalars);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_moments(const Plan& P, const void* psi, const void* psi_cl, const tw_moments_out* out,
+                          const double* energy_dev, hipStream_t s) {
+  const MomGeom G{P.p.n_real, P.ncell, P.p.m_tot, P.dV, P.p.n_tot, P.fp32};
+  return launch_moments_geom(G, P.partial, psi, psi_cl, out, energy_dev, s);
 }
 
 // Energy assembly: E_f = m_tot [ (hbar^2/2) dV sum_a KS_a / n_a + (1/2) dV PS ]

@@ -34,13 +34,8 @@ static hipError_t launch_pass_tnr(int mode, const PassArgs& a, hipStream_t s, in
   dim3 block(pass_threads<T, N, ROWS>());
   auto go = [&](auto kern) -> hipError_t {
     if constexpr (LDS > 64 * 1024) {
-      static bool attr_set = false;  // per instantiation, once per process
-      if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-      }
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), LDS);
+      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, grid, block, LDS, s, a);
     return hipGetLastError();
@@ -167,7 +162,7 @@ __global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N))
     for (int m = 0; m < R; ++m) zv[m] = mul_d(zv[m], g[m]);
     fft_pencil<T, N, true, true>(zv, lds, t, tc);
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], expmi<T>(kick * (double)zv[m].re));
+    for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], (kick * (double)zv[m].re));
     drift(s + 1 < nsteps ? ph_full : ph_half);
   }
   if (active) {

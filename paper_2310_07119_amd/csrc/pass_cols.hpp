@@ -249,7 +249,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         if constexpr (MODE == PASS_KICK_DRIFT) {
 #pragma unroll
           for (int m = 0; m < R; ++m) {
-            v[m] = cmul(v[m], expmi<T>(kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
+            v[m] = kick_rotate<T>(v[m], (kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
           }
           drift(q, v);
           pencil_put(q, v);

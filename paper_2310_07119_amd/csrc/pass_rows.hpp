@@ -184,14 +184,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      va[m] = cmul(va[m], expmi<T>(kick * (double)zv[m].re));
+      va[m] = kick_rotate<T>(va[m], (kick * (double)zv[m].re));
     }
     drift(va);
     store_psi(fA, va);
     if (hasB) {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        vb[m] = cmul(vb[m], expmi<T>(kick * (double)zv[m].im));
+        vb[m] = kick_rotate<T>(vb[m], (kick * (double)zv[m].im));
       }
       drift(vb);
       store_psi(fB, vb);

@@ -29,7 +29,7 @@ EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_step
            "tw_batch_destroy", "tw_fno_param_count", "tw_fno_create", "tw_fno_destroy", "tw_fno_init_params",
            "tw_fno_forward", "tw_fno_backward", "tw_fno_mse", "tw_fno_adam", "tw_fno_last_error",
            "tw_plan_set_profiling", "tw_plan_get_profile", "tw_kernel_kind_name", "tw_last_error")
-NUM_KERNEL_KINDS = 16
+NUM_KERNEL_KINDS = 20
 
 
 class TwProblem(ctypes.Structure):
