@@ -199,6 +199,26 @@ typedef struct {
 int tw_moments(tw_plan plan, const void* psi, const void* psi_classical,
                const tw_moments_out* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the moment
+ * reductions of tw_moments without a plan. Computes mean_psi, mean_abs2,
+ * mean_rho, var_rho, norm and scalars exactly as tw_moments does (same
+ * kernels; scalars[4] and scalars[7] are 0, as tw_moments gives them without
+ * energies). Allocates nothing: its partial sums live in a fixed 32 MiB device
+ * array of the library, one per GPU, held until the process ends, so
+ *   n_real * ceil(N/64) + 3 * ceil(N/64) + n_real + 3 <= 4194304
+ * (e.g. 512^2 with 256 realizations, 128^3 with 64) or TW_EUNSUPPORTED before
+ * any launch. energy, mode_occ, var_amp, var_phase and decoherence must be
+ * NULL (TW_EUNSUPPORTED: they need a plan's spectral scratch). Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (two streams,
+ * two threads) race and must be ordered by the caller; the array keeps the
+ * last call's partial sums, none of which a call reads before writing it.
+ *   p             : the problem (grid, box, m_tot, n_tot, n_real, precision),
+ *                   validated as by tw_plan_create except the FFT lengths.
+ *   psi, psi_classical, out, stream : as tw_moments. */
+int tw_moments_static(const tw_problem* p, const void* psi, const void* psi_classical,
+                      const tw_moments_out* out, void* stream);
+
 /* Autotune the kernel organisation of the passes along strided axes (y, z).
  * Returns at once if the plan's choice is already settled (tuning cache entry,
  * TW_COLS_VARIANT override, or an earlier call). Optional: TW_STREAMS=2 in the

@@ -24,7 +24,8 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
 # fixed sequence of correctly rounded operations.
 PER_FILE = {"kernels_sample.hip": ["-ffp-contract=off"]}
 SOURCES = ["api.hip", "tune.hip", "kernels_step.hip", "kernels_cols.hip", "kernels_slab.hip", "kernels_batch.hip",
-           "kernels_sample.hip", "kernels_moments.hip", "kernels_tracers.hip", "kernels_fno.hip", "fno.hip"]
+           "kernels_sample.hip", "kernels_moments.hip", "kernels_tracers.hip", "kernels_fno.hip", "fno.hip",
+           "noalloc.hip"]
 
 
 def _compile(src):

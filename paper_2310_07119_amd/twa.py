@@ -24,7 +24,7 @@ SCALAR_NAMES = ("Q_raw", "Q_sym", "dev_rho_L1", "dev_psi_L2", "energy_mean", "no
 
 # Exported entry points and their argument types (mirrors include/tw.h).
 EXPORTS = ("tw_plan_create", "tw_plan_destroy", "tw_sample", "tw_step", "tw_step_adaptive", "tw_step_tracers",
-           "tw_tracer_spread", "tw_moments",
+           "tw_tracer_spread", "tw_moments", "tw_moments_static",
            "tw_plan_autotune", "tw_batch_create", "tw_batch_plan", "tw_batch_autotune", "tw_batch_step",
            "tw_batch_destroy", "tw_fno_param_count", "tw_fno_create", "tw_fno_destroy", "tw_fno_init_params",
            "tw_fno_forward", "tw_fno_backward", "tw_fno_mse", "tw_fno_adam", "tw_fno_last_error",
@@ -72,6 +72,7 @@ def load_library(path=LIB_PATH):
     lib.tw_step_tracers.argtypes = [vp, vp, vp, i64, dbl, vp, i64, vp]
     lib.tw_tracer_spread.argtypes = [vp, vp, i64, vp, vp]
     lib.tw_moments.argtypes = [vp, vp, vp, ctypes.POINTER(TwMomentsOut), vp]
+    lib.tw_moments_static.argtypes = [ctypes.POINTER(TwProblem), vp, vp, ctypes.POINTER(TwMomentsOut), vp]
     lib.tw_plan_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.tw_batch_create.argtypes = [ctypes.POINTER(TwProblem), ctypes.c_int32, ctypes.POINTER(vp)]
     lib.tw_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -322,6 +323,32 @@ class Plan:
         if deco is not None:
             out["Var_A"], out["Var_phi"] = deco.cpu().tolist()
         return out
+
+
+def moments_static(problem: Problem, psi, psi_classical=None, out=None):
+    """Moment reductions without a plan (tw_moments_static): mean_psi,
+    mean_abs2, mean_rho, var_rho, norm and the scalars, into the caller's
+    device tensors `out` (a dict with those keys plus "scalars" [8]; allocated
+    here if None). The library call itself allocates nothing."""
+    lib = load_library()
+    p = problem
+    assert psi.dtype == p.cdtype and psi.is_contiguous()
+    if psi_classical is not None:
+        assert psi_classical.dtype == p.cdtype and psi_classical.is_contiguous()
+    if out is None:
+        dev = psi.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = {"mean_psi": torch.empty(p.shape, dtype=torch.complex128, device=dev),
+               "mean_abs2": torch.empty(p.shape, **f64), "mean_rho": torch.empty(p.shape, **f64),
+               "var_rho": torch.empty(p.shape, **f64), "norm": torch.empty(p.n_real, **f64),
+               "scalars": torch.empty(8, **f64)}
+    mo = TwMomentsOut()
+    for k in ("mean_psi", "mean_abs2", "mean_rho", "var_rho", "norm", "scalars"):
+        setattr(mo, k, out[k].data_ptr() if out.get(k) is not None else None)
+    pr = _problem_struct(p)
+    _check(lib.tw_moments_static(ctypes.byref(pr), _ptr(psi), _ptr(psi_classical), ctypes.byref(mo), _stream()),
+           "tw_moments_static")
+    return out
 
 
 class Batch:
