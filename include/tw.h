@@ -132,8 +132,10 @@ int tw_step(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double
  *   courant : c_f in (0, 1].
  *   dt_out  : device, [nsteps] doubles receiving dt_n (the elapsed time is their
  *             sum), or NULL; 8-byte aligned (else TW_ELAYOUT).
- * D >= 2 only (TW_EUNSUPPORTED for D = 1, whose fields are advanced by a
- * resident kernel that never leaves the workgroup). Other arguments as tw_step. */
+ * D = 1 runs one launch per step (each field inside one workgroup) instead
+ * of tw_step's single resident launch, so that max|V| can cross the ensemble
+ * between steps. D >= 2 needs every axis >= 16 points (TW_EUNSUPPORTED
+ * otherwise). Other arguments as tw_step. */
 int tw_step_adaptive(tw_plan plan, void* psi, void* psi_classical, int64_t nsteps, double dt_max,
                      double courant, double* dt_out, void* stream);
 

@@ -95,22 +95,6 @@ hipError_t timed(Plan& P, int kind, hipStream_t s, F&& f) {
   return e != hipSuccess ? e : e2;
 }
 
-// How often one transform of length n multiplies by each entry of the
-// twiddle table: stage s of radix Rs (Ns the product of the earlier radices)
-// multiplies input r >= 1 of butterfly j by W_n^(r (j mod Ns) n / (Ns Rs)).
-std::vector<double> twiddle_uses(int n) {
-  std::vector<double> w(n, 0.0);
-  const int R = fft_points_per_thread(n);
-  const int S = fft_num_stages(n, R);
-  for (int st = 0; st < S; ++st) {
-    const int rs = fft_stage_radix(n, R, st), nsb = fft_stage_ns(n, R, st);
-    if (nsb == 1) continue;
-    for (int j = 0; j < n / rs; ++j)
-      for (int r = 1; r < rs; ++r) w[(size_t)r * (j % nsb) * (n / (nsb * rs))] += 1.0;
-  }
-  return w;
-}
-
 int64_t axis_stride(const Plan& P, int axis) {
   if (axis == 0) return 1;
   if (axis == 1) return P.n[0];
@@ -276,6 +260,29 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
     TW_HIP(timed(P, KIND_MEAN, s, [&] { return launch_field_mean(P, psi, psi_cl, nfield, P.rho_mean, s); }));
   const double kick = dt / P.p.hbar_m;
 
+  if (P.dim == 1 && ad) {
+    // device-chosen steps: one launch per step, max |V| buckets and step
+    // sizes exactly as for D >= 2 (steps 0 and 1 from the fields on entry,
+    // step n + 2 from the potential inside step n)
+    TW_HIP(timed(P, KIND_TABLES, s, [&] { return launch_adapt_clear(P, s); }));
+    TW_HIP(timed(P, KIND_STEP1D, s, [&] {
+      return launch_step1d_adapt(P, psi, psi_cl, nfield, -1, nullptr, nullptr, nullptr,
+                                 P.adapt + kAdaptScalars + 2 * kVmaxBuckets, s);
+    }));
+    TW_HIP(timed(P, KIND_TABLES, s, [&] {
+      return launch_adapt(P, -1, nsteps == 1, ad->dt_max, ad->courant, ad->dtk, ad->dt_out, s);
+    }));
+    for (int64_t st = 0; st < nsteps; ++st) {
+      TW_HIP(timed(P, KIND_STEP1D, s, [&] {
+        return launch_step1d_adapt(P, psi, psi_cl, nfield, st, ph_open(0), ph_step(0, st, st + 1 == nsteps),
+                                   P.adapt + 6 + st % 2, P.adapt + kAdaptScalars + (st % 3) * kVmaxBuckets, s);
+      }));
+      TW_HIP(timed(P, KIND_TABLES, s, [&] {
+        return launch_adapt(P, st, st + 2 == nsteps, ad->dt_max, ad->courant, ad->dtk, ad->dt_out, s);
+      }));
+    }
+    return TW_OK;
+  }
   if (P.dim == 1) {
     TW_HIP(timed(P, KIND_STEP1D, s, [&] {
       return launch_step1d(P, psi, psi_cl, nfield, nsteps, phase_slot(0, 0), phase_slot(0, 1), kick, s);
@@ -567,10 +574,6 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   } while (0)
 
   // twiddle and wavenumber tables per axis
-  // search radius of the FP32 twiddle rounding below (measured on the 3D
-  // 128^3 run: one unit takes the FP32 norm drift from 2.9e-5 to 2.0e-5 over
-  // 2000 steps; two or three units gain nothing more and lose angle accuracy)
-  constexpr int kTwiddleUlps = 1;
   for (int d = 0; d < 3; ++d) {
     const int n = P->n[d];
     std::vector<double> k2(n);
@@ -591,43 +594,17 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
       tw2[2 * e + 1] = (double)sinl(ang);
     }
     if (P->fp32) {
-      // FP32 twiddles: each entry is one of the float pairs within
-      // kTwiddleUlps units in the last place of (cos, sin). A transform scales
-      // the norm of its input by 1 + (mean of |w|^2 - 1 over the twiddle
-      // multiplications it makes), so the entries are chosen in turn to keep
-      // the usage-weighted sum of |w|^2 - 1 over one transform closest to 0
-      // (ties: the pair nearer to the exact value). Rounding each pair to the
-      // modulus nearest 1 instead left -1e-8 per 128- or 512-point transform,
-      // which shrank every FP32 field's norm by 2e-4 over the 5000 steps of
-      // the 2D benchmark workload; balanced, the bias is about 1e-10 or less.
-      const std::vector<double> uses = d < pr->dim ? twiddle_uses(n) : std::vector<double>(n, 0.0);
+      // FP32 twiddles as shear pairs (fft.hpp): entry e holds (tan(phi/2),
+      // sin phi) of the angle -2 pi e / n reduced to |phi| <= pi/2, by a half
+      // turn (a sign flip the kernels read off the index) and/or a whole turn
       std::vector<float> tf(2 * n);
-      long double acc = 0.0L;  // weighted sum of |w|^2 - 1 so far
+      const long double two_pi = 6.283185307179586476925286766559005768L;
       for (int e = 0; e < n; ++e) {
-        const float c0 = (float)tw2[2 * e], s0 = (float)tw2[2 * e + 1];
-        float bc = c0, bs = s0;
-        long double best_key = -1.0L, best_dist = 0.0L, best_dev = 0.0L;
-        auto step = [](float x, int k) {
-          for (int i = 0; i < (k < 0 ? -k : k); ++i) x = std::nextafter(x, k > 0 ? 2.0f : -2.0f);
-          return x;
-        };
-        for (int dc = -kTwiddleUlps; dc <= kTwiddleUlps; ++dc)
-          for (int ds = -kTwiddleUlps; ds <= kTwiddleUlps; ++ds) {
-            const float c = step(c0, dc), sn = step(s0, ds);
-            const long double dev = (long double)c * c + (long double)sn * sn - 1.0L;
-            const long double key = uses[e] > 0.0 ? fabsl(acc + uses[e] * dev) : fabsl(dev);
-            const long double dist = fabsl((long double)c - tw2[2 * e]) + fabsl((long double)sn - tw2[2 * e + 1]);
-            if (best_key < 0.0L || key < best_key || (key == best_key && dist < best_dist)) {
-              best_key = key;
-              best_dist = dist;
-              best_dev = dev;
-              bc = c;
-              bs = sn;
-            }
-          }
-        acc += uses[e] * best_dev;
-        tf[2 * e] = bc;
-        tf[2 * e + 1] = bs;
+        long double phi = -two_pi * (long double)e / (long double)n;
+        if (twiddle_flip(e, n)) phi += 0.5L * two_pi;
+        else if (4 * e >= 3 * n) phi += two_pi;
+        tf[2 * e] = (float)tanl(0.5L * phi);
+        tf[2 * e + 1] = (float)sinl(phi);
       }
       ALLOC(P->twd[d], sizeof(float) * 2 * n);
       if (hipMemcpy(P->twd[d], tf.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
@@ -693,10 +670,8 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
   P->partial_len = (size_t)std::max<int64_t>(energy_part + mom_part, P->nfield * kFieldMeanParts);
   ALLOC(P->partial, sizeof(double) * P->partial_len);
   ALLOC(P->scratch_small, sizeof(double) * 64);
-  if (pr->dim >= 2) {
-    ALLOC(P->adapt, sizeof(double) * (kAdaptScalars + 3 * kVmaxBuckets));
-    ALLOC(P->adapt_tab, sizeof(double) * 2 * 3 * 3 * (size_t)P->nmax);
-  }
+  ALLOC(P->adapt, sizeof(double) * (kAdaptScalars + 3 * kVmaxBuckets));
+  ALLOC(P->adapt_tab, sizeof(double) * 2 * 3 * 3 * (size_t)P->nmax);
 #undef ALLOC
   *out = reinterpret_cast<tw_plan>(P);
   return TW_OK;
@@ -794,7 +769,7 @@ int tw_step_adaptive(tw_plan plan, void* psi, void* psi_cl, int64_t nsteps, doub
   if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(TW_EINVAL, "dt_max must be positive and finite");
   if (!(courant > 0.0) || !(courant <= 1.0)) return fail(TW_EINVAL, "courant must be in (0, 1]");
   if (reinterpret_cast<uintptr_t>(dt_out) % 8 != 0) return fail(TW_ELAYOUT, "dt_out must be 8-byte aligned");
-  if (P.dim < 2 || !P.z || !P.adapt) return fail(TW_EUNSUPPORTED, "adaptive steps need D >= 2 (all axes >= 16 points)");
+  if (!P.adapt || (P.dim >= 2 && !P.z)) return fail(TW_EUNSUPPORTED, "adaptive steps need all axes >= 16 points for D >= 2");
   if (P.chunk_pairs > 0 && P.chunk_pairs < P.npairs)
     return fail(TW_EUNSUPPORTED, "adaptive steps need the whole ensemble in one chunk (TW_CHUNK_PAIRS)");
   if (nsteps == 0) return TW_OK;

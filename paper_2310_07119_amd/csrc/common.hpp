@@ -149,11 +149,13 @@ __device__ __forceinline__ cx<T> expmi(double arg) {
 }
 
 // The kick psi <- psi exp(-i arg) (Sec. "Integrating the equations of motion").
-// FP64: the product with the factor of expmi. FP32: psi + psi ((cos arg - 1)
-// - i sin arg), with cos arg - 1 kept to full relative precision. Formed as
-// cos arg rounded to float, the factor's modulus exceeds 1 by arg^2 for every
-// |arg| below about 2.4e-4 (cos rounds to exactly 1), a bias that grew the
-// norm of every FP32 field by about 1e-8 per step at typical kick phases.
+// FP64: the product with the factor of expmi. FP32: exp(-i arg) = (-i)^q
+// exp(-i r) with arg = q pi/2 + r, |r| <= pi/4 (FP64 reduction): the quarter
+// turns are exact swaps and sign changes, and exp(-i r) is applied as three
+// shears, x -= t y, y -= s x, x -= t y with s = sin r, t = tan(r/2) =
+// s / (1 + cos r), each of determinant 1 whatever s and t round to. A factor
+// formed as (cos, sin) rounded to float instead has |f|^2 - 1 up to 6e-8 (for
+// |r| below 2.4e-4 cos rounds to exactly 1 and every kick grew the norm by r^2).
 __device__ __forceinline__ void sincos_m1_series(float x, float& s, float& cm1) {
   const float x2 = x * x;
   float ps = 1.f / 362880.f;
@@ -174,29 +176,30 @@ __device__ __forceinline__ cx<T> kick_rotate(cx<T> v, double arg) {
   if constexpr (sizeof(T) == 8) {
     return cmul(v, expmi<T>(arg));
   } else {
-    float s, cm1;  // sin(arg), cos(arg) - 1
-    if (fabs(arg) <= 0.78539816339744830962) {
-      sincos_m1_series((float)arg, s, cm1);
-    } else if (fabs(arg) <= 1.0e6) {
-      int q;
-      const double r = quarter_turns(arg, q);
-      float sr, cr1;
-      sincos_m1_series((float)r, sr, cr1);
-      switch (q) {
-        case 0: s = sr; cm1 = cr1; break;
-        case 1: s = 1.f + cr1; cm1 = -sr - 1.f; break;
-        case 2: s = -sr; cm1 = -2.f - cr1; break;
-        default: s = -(1.f + cr1); cm1 = sr - 1.f; break;
+    int q = 0;
+    double r = arg;
+    if (fabs(arg) > 0.78539816339744830962) {
+      if (fabs(arg) > 1.0e6) {
+        const double two_pi = 6.283185307179586476925286766559;
+        r = arg - two_pi * rint(arg * (1.0 / two_pi));
       }
-    } else {
-      const double two_pi = 6.283185307179586476925286766559;
-      const double r = arg - two_pi * rint(arg * (1.0 / two_pi));
-      float cf;
-      sincosf((float)r, &s, &cf);
-      cm1 = cf - 1.f;
+      r = quarter_turns(r, q);
     }
-    // (re + i im)(1 + cm1 - i s)
-    return {v.re + (v.re * cm1 + v.im * s), v.im + (v.im * cm1 - v.re * s)};
+    cx<float> w = v;
+    switch (q) {  // times (-i)^q
+      case 1: w = {v.im, -v.re}; break;
+      case 2: w = {-v.re, -v.im}; break;
+      case 3: w = {-v.im, v.re}; break;
+      default: break;
+    }
+    float s, cm1;
+    sincos_m1_series((float)r, s, cm1);
+    const float t = s * __builtin_amdgcn_rcpf(2.f + cm1);
+    // rotation by -r
+    const float x1 = __builtin_fmaf(t, w.im, w.re);
+    const float y1 = __builtin_fmaf(-s, x1, w.im);
+    const float x2 = __builtin_fmaf(t, y1, x1);
+    return {x2, y1};
   }
 }
 

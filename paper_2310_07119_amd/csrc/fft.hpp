@@ -147,11 +147,26 @@ struct Butterfly<T, 6, INV> {
     cx<T> o0 = v[i0 + step], o1 = v[i0 + 3 * step], o2 = v[i0 + 5 * step];
     Butterfly<T, 3, INV>::dft3(e0, e1, e2);
     Butterfly<T, 3, INV>::dft3(o0, o1, o2);
-    const T h = (T)0.86602540378443864676372317075294;
     // W6 = 1/2 -+ i sqrt3/2, W6^2 = -1/2 -+ i sqrt3/2 (forward sign first)
-    const cx<T> w1 = INV ? cx<T>{(T)0.5, h} : cx<T>{(T)0.5, -h};
-    const cx<T> w2 = INV ? cx<T>{(T)-0.5, h} : cx<T>{(T)-0.5, -h};
-    const cx<T> p1 = cmul(o1, w1), p2 = cmul(o2, w2);
+    cx<T> p1, p2;
+    if constexpr (sizeof(T) == 4) {
+      // x sqrt3/2 as a float pair rounded once (a single float constant
+      // makes |W6| differ from 1 by 2.7e-8 and scales every transform's norm)
+      auto h = [](float x) { return __builtin_fmaf(0.8660254f, x, 1.5543625e-08f * x); };
+      if constexpr (!INV) {
+        p1 = {0.5f * o1.re + h(o1.im), 0.5f * o1.im - h(o1.re)};
+        p2 = {h(o2.im) - 0.5f * o2.re, -0.5f * o2.im - h(o2.re)};
+      } else {
+        p1 = {0.5f * o1.re - h(o1.im), 0.5f * o1.im + h(o1.re)};
+        p2 = {-0.5f * o2.re - h(o2.im), h(o2.re) - 0.5f * o2.im};
+      }
+    } else {
+      const T h = (T)0.86602540378443864676372317075294;
+      const cx<T> w1 = INV ? cx<T>{(T)0.5, h} : cx<T>{(T)0.5, -h};
+      const cx<T> w2 = INV ? cx<T>{(T)-0.5, h} : cx<T>{(T)-0.5, -h};
+      p1 = cmul(o1, w1);
+      p2 = cmul(o2, w2);
+    }
     v[i0] = e0 + o0;
     v[i0 + 3 * step] = e0 - o0;
     v[i0 + step] = e1 + p1;
@@ -203,12 +218,36 @@ struct Butterfly<T, 8, INV> {
   }
 };
 
+// ------------------------------------------------------- FP32 rotations
+// FP32 twiddle multiplications are rotations by three shears, exp(i phi) =
+// X(-t) Y(s) X(-t) with t = tan(phi/2), s = sin phi, X(a) = [[1, a], [0, 1]],
+// Y(b) = [[1, 0], [b, 1]] (Paeth's decomposition). Every shear has
+// determinant 1 whatever t and s round to, so the product changes no input's
+// norm systematically. A float pair (cos, sin) instead has |w|^2 - 1 up to
+// 6e-8 (near the axes no neighbouring pair does better), and the FP32
+// transforms shrank the fields' norms by 1e-9 to 1e-8 per transform depending
+// on where the field's energy sat. The FP32 table holds (t, s) of the angle
+// reduced to |phi| <= pi/2; entries whose angle was beyond pi/2 are -exp(i phi)
+// (flip), which the index tells: 4e in (N, 3N). Inverse transforms rotate by -phi.
+__host__ __device__ constexpr bool twiddle_flip(int e, int N) { return 4 * e > N && 4 * e < 3 * N; }
+
+template <bool INV>
+__device__ __forceinline__ cx<float> shear_rotate(cx<float> v, float t, float s, bool flip) {
+  const float tt = INV ? t : -t;
+  const float ss = INV ? -s : s;
+  const float x1 = __builtin_fmaf(tt, v.im, v.re);
+  const float y1 = __builtin_fmaf(ss, x1, v.im);
+  const float x2 = __builtin_fmaf(tt, y1, x1);
+  return flip ? cx<float>{-x2, -y1} : cx<float>{x2, y1};
+}
+
 // --------------------------------------------------------- twiddle cache
 // Per-thread twiddles of every stage, loaded once from the table into
 // registers (a thread's butterfly indices are the same for every pencil it
 // transforms). Stage s, butterfly i, input r >= 1 uses W_N^(r (j mod Ns) N/(Ns Rs)).
 // With CACHED = false only the table pointer is kept and each stage reads its
 // twiddles when it runs (fewer registers, more memory latency per stage).
+// FP64 tables hold (cos, sin); FP32 tables the shear pairs above.
 template <class T, int N, bool CACHED_ = true>
 struct TwiddleCache {
   static constexpr bool CACHED = CACHED_;
@@ -234,16 +273,30 @@ struct TwiddleCache {
     t_ = t;
     if constexpr (CACHED) load_stage<0>(twd, t);
   }
+  // table index of the twiddle of stage S, butterfly i, input r
+  template <int S>
+  __device__ __forceinline__ int index(int i, int r) const {
+    constexpr int RS = fft_stage_radix(N, R, S);
+    constexpr int NSB = fft_stage_ns(N, R, S);
+    return r * ((t_ + TPP * i) % NSB) * (N / (NSB * RS));
+  }
   // twiddle for stage S, butterfly i, input r
   template <int S>
   __device__ __forceinline__ cx<T> get(int i, int r) const {
     if constexpr (CACHED) {
       return w[stage_offset(S) + i * (fft_stage_radix(N, R, S) - 1) + (r - 1)];
     } else {
-      constexpr int RS = fft_stage_radix(N, R, S);
-      constexpr int NSB = fft_stage_ns(N, R, S);
-      const int jm = (t_ + TPP * i) % NSB;
-      return table[r * jm * (N / (NSB * RS))];
+      return table[index<S>(i, r)];
+    }
+  }
+  // v <- v W (forward) or v conj(W) (inverse) for stage S, butterfly i, input r
+  template <int S, bool INV>
+  __device__ __forceinline__ void apply(cx<T>& v, int i, int r) const {
+    const cx<T> w = get<S>(i, r);
+    if constexpr (sizeof(T) == 8) {
+      v = INV ? cmulc(v, w) : cmul(v, w);
+    } else {
+      v = shear_rotate<INV>(v, w.re, w.im, twiddle_flip(index<S>(i, r), N));
     }
   }
   template <int S>
@@ -301,10 +354,7 @@ struct FftStage {
     for (int i = 0; i < NB; ++i) {
       if constexpr (NSB > 1) {
 #pragma unroll
-        for (int r = 1; r < RS; ++r) {
-          const cx<T> w = tc.template get<S>(i, r);  // TwiddleCache<T, N, cached>
-          v[i + r * NB] = INV ? cmulc(v[i + r * NB], w) : cmul(v[i + r * NB], w);
-        }
+        for (int r = 1; r < RS; ++r) tc.template apply<S, INV>(v[i + r * NB], i, r);  // TwiddleCache<T, N, cached>
       }
       Butterfly<T, RS, INV>::run(v, i, NB);
     }

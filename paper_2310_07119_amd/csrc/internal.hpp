@@ -133,6 +133,11 @@ size_t slab_lds_bytes(int n, bool fp32);
 int cols_pencils_per_group(int n, bool fp32);
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* phase_half, const void* phase_full, double kick, hipStream_t s);
+// D = 1 with device-chosen steps: one step (or, with step < 0, the initial
+// potential only) of every field per launch; records max |V| into vmax.
+hipError_t launch_step1d_adapt(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t step,
+                               const void* ph_open, const void* ph_step, const double* kick_dev, double* vmax,
+                               hipStream_t s);
 hipError_t launch_phase_table(const Plan& P, int axis, double tau, void* out, hipStream_t s);
 // Adaptive time step: after the kick pass of step `step` (or, with step = -1,
 // after the initial potential), choose the size of step + 2 (steps 0 and 1)

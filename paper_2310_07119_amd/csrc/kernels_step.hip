@@ -199,6 +199,104 @@ static hipError_t launch_step1d_t(const Plan& P, void* psi, void* psi_cl, int64_
 
 bool step1d_length_supported(int n) { return n == 8 || pass_length_supported(n); }
 
+// D = 1 with device-chosen step sizes: one launch per step (each field still
+// in one workgroup), so that the ensemble-wide max |V| of step n can size step
+// n + 2 between launches (adapt_kernel). step < 0: only the potential of the
+// fields on entry, its max |V| recorded, nothing stored. step >= 0: the
+// opening half drift (step 0 only), density, potential (max |V| recorded),
+// kick with the factor in kick_dev, then the drift of ph_step (merged with the
+// next step's first half, or the closing half drift).
+template <class T, int N>
+__global__ void __launch_bounds__((fields_per_group_1d<T, N>() * fft_threads(N)))
+    step1d_adapt_kernel(void* psi, void* psi_cl, int64_t n_real, int64_t nfield, int64_t step,
+                        const cx<T>* __restrict__ twd, const double* __restrict__ k2,
+                        const cx<double>* __restrict__ ph_open, const cx<double>* __restrict__ ph_step, double green,
+                        const double* __restrict__ kick_dev, double m_tot, const double* __restrict__ rho_mean,
+                        double* vmax) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int R = N / TPP;
+  constexpr int C = fields_per_group_1d<T, N>();
+  __shared__ cx<T> lds_all[C * fft_lds_stride(N)];
+  __shared__ double red[16];
+  const int c = threadIdx.x / TPP;
+  const int t = threadIdx.x % TPP;
+  cx<T>* lds = lds_all + c * fft_lds_stride(N);
+  const int64_t f = (int64_t)blockIdx.x * C + c;
+  const bool active = f < nfield;
+  cx<T>* fp = !active ? nullptr
+              : (f < n_real ? reinterpret_cast<cx<T>*>(psi) + f * N : reinterpret_cast<cx<T>*>(psi_cl));
+  const double mean = (active && rho_mean) ? rho_mean[f] : 0.0;
+  TwiddleCache<T, N> tc;
+  tc.load(twd, t);
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = active ? fp[t + TPP * m] : cx<T>{(T)0, (T)0};
+  auto drift = [&](const cx<double>* ph) {
+    fft_pencil<T, N, false, true>(v, lds, t, tc);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
+    fft_pencil<T, N, true, true>(v, lds, t, tc);
+  };
+  if (step == 0) drift(ph_open);
+  cx<T> zv[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) zv[m] = {(T)(m_tot * (double)abs2(v[m]) - mean), (T)0};
+  fft_pencil<T, N, false, true>(zv, lds, t, tc);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const double kk = k2[t + TPP * m];
+    zv[m] = mul_d(zv[m], (kk == 0.0) ? 0.0 : green / kk);
+  }
+  fft_pencil<T, N, true, true>(zv, lds, t, tc);
+  double mx = 0.0;
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) mx = fmax(mx, fabs((double)zv[m].re));
+  }
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) record_max(vmax + (blockIdx.x & (kVmaxBuckets - 1)), mx);
+  if (step < 0) return;
+  const double kick = kick_dev[0];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], kick * (double)zv[m].re);
+  drift(ph_step);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) fp[t + TPP * m] = v[m];
+  }
+}
+
+template <class T, int N>
+static hipError_t launch_step1d_adapt_tn(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t step,
+                                         const void* ph_open, const void* ph_step, const double* kick_dev,
+                                         double* vmax, hipStream_t s) {
+  constexpr int TPP = fft_threads(N);
+  constexpr int C = fields_per_group_1d<T, N>();
+  dim3 grid((unsigned)((nfield + C - 1) / C)), block(C * TPP);
+  const double green = -4.0 * M_PI * P.p.G / (double)N;
+  hipLaunchKernelGGL((step1d_adapt_kernel<T, N>), grid, block, 0, s, psi, psi_cl, (int64_t)P.p.n_real, nfield, step,
+                     reinterpret_cast<const cx<T>*>(P.twd[0]), P.k2[0], reinterpret_cast<const cx<double>*>(ph_open),
+                     reinterpret_cast<const cx<double>*>(ph_step), green, kick_dev, P.p.m_tot,
+                     P.fp32 ? P.rho_mean : nullptr, vmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_step1d_adapt(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t step,
+                               const void* ph_open, const void* ph_step, const double* kick_dev, double* vmax,
+                               hipStream_t s) {
+  auto go = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    switch (P.n[0]) {
+#define TW_CASE(L) \
+  case L: return launch_step1d_adapt_tn<T, L>(P, psi, psi_cl, nfield, step, ph_open, ph_step, kick_dev, vmax, s);
+      TW_STEP1D_LENGTHS(TW_CASE)
+#undef TW_CASE
+      default: return hipErrorInvalidValue;
+    }
+  };
+  return P.fp32 ? go(float{}) : go(double{});
+}
+
 hipError_t launch_step1d(const Plan& P, void* psi, void* psi_cl, int64_t nfield, int64_t nsteps,
                          const void* ph_half, const void* ph_full, double kick, hipStream_t s) {
   return P.fp32 ? launch_step1d_t<float>(P, psi, psi_cl, nfield, nsteps, ph_half, ph_full, kick, s)

@@ -81,13 +81,90 @@ def test_potential_bound_vs_oracle(case, precision, transpose, monkeypatch):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_1d_free_field_equals_resident_steps(precision):
+    """D = 1, G = 0: every step is dt_max, and the per-step launches of the
+    adaptive path give the resident kernel's fields bit for bit."""
+    p = Problem(n=(256,), hbar_m=0.8, G=0.0, n_tot=1e4, n_real=5, precision=precision)
+    psi_cl = inputs.lognormal_field(p.n, p.box, kcut=16, seed=2)
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    a = plan.sample(cl, 9)
+    b = a.clone()
+    ca = cl.to(p.cdtype).clone()
+    cb = ca.clone()
+    dts = plan.step_adaptive(a, 6, 1e-4, courant=0.5, psi_classical=ca)
+    plan.step(b, 6, 1e-4, cb)
+    torch.cuda.synchronize()
+    assert torch.all(dts == 1e-4)
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nr,m_tot", [((256,), 9, 30.0), ((96,), 4, 30.0), ((1024,), 3, 300.0)],
+                         ids=["256", "96", "1024"])
+def test_1d_potential_bound_vs_oracle(n, nr, m_tot, precision):
+    """D = 1 with strong gravity: the potential bound sets and changes the
+    step sizes (one launch per step, max |V| over the whole ensemble)."""
+    p = Problem(n=n, hbar_m=0.05, G=1.0, m_tot=m_tot, n_tot=1e5, n_real=nr, precision=precision)
+    psi_cl = inputs.lognormal_field(n, p.box, kcut=min(n) // 4, seed=5)
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 77)
+    clt = cl.to(p.cdtype).clone()
+    psi0 = psi.cpu().numpy().astype(np.complex128)
+    print(f"adaptive 1D {n} {precision}", flush=True)
+    dts = plan.step_adaptive(psi, 9, 1.0, courant=0.5, psi_classical=clt).cpu().numpy()
+    torch.cuda.synchronize()
+    prob = oracle_problem(p)
+    cl0 = psi_cl if precision == "fp64" else psi_cl.astype(np.complex64).astype(np.complex128)
+    ref, rdts = tw.evolve_adaptive(prob, np.concatenate([psi0, cl0[None]]), 9, 1.0, 0.5)
+    assert len(set(rdts.tolist())) > 2, "the potential bound should bind and vary"
+    tol = TOL[precision]
+    assert rel(dts, rdts) < (1e-12 if precision == "fp64" else 1e-5)
+    assert rel(psi.cpu().numpy(), ref[:nr]) < tol
+    assert rel(clt.cpu().numpy(), ref[nr]) < tol
+    plan.close()
+
+
+def test_1d_sinusoid_workload_full_run():
+    """The paper's sinusoidal overdensity (Sec. "Sinusoidal overdensity") as
+    the 1D workload: 512 points, L = 60 kpc, M_tot = 1e8 M_sun, hbar/m = 0.01
+    kpc^2/Myr, n_tot = 1e6, 64 realizations + the classical field, 1000 steps
+    chosen on the device (dt_max = 10 Myr, c_f = 0.5; they shrink to about 2 Myr
+    as the overdensity collapses). Fields, step sizes and moments against the
+    oracle's adaptive evolution at 1e-10 (FP64; the oracle's own sensitivity
+    to a 1e-15 perturbation over this run is 1.4e-11)."""
+    w = inputs.WORKLOADS["1d_sinusoid"]
+    p = Problem(n=w["n"], box=w["box"], hbar_m=w["hbar_m"], G=w["G"], m_tot=w["m_tot"], n_tot=w["n_tot"],
+                n_real=w["n_real"], precision="fp64")
+    psi_cl = inputs.initial_field("1d_sinusoid")
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 5)
+    clt = cl.clone()
+    psi0 = psi.cpu().numpy()
+    print("1d sinusoid workload, 1000 adaptive steps", flush=True)
+    dts = plan.step_adaptive(psi, w["nsteps"], w["dt"], courant=0.5, psi_classical=clt).cpu().numpy()
+    m = plan.moments(psi, clt)
+    torch.cuda.synchronize()
+    prob = oracle_problem(p)
+    ref, rdts = tw.evolve_adaptive(prob, np.concatenate([psi0, psi_cl[None]]), w["nsteps"], w["dt"], 0.5)
+    assert rdts.min() < 0.5 * w["dt"], "the collapse should shrink the steps"
+    assert rel(dts, rdts) < 1e-12
+    assert rel(psi.cpu().numpy(), ref[:-1]) < 1e-10
+    assert rel(clt.cpu().numpy(), ref[-1]) < 1e-10
+    mo = tw.moments(prob, ref[:-1], p.n_tot, ref[-1])
+    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
+        assert rel(m[k].cpu().numpy(), mo[k]) < 1e-10, k
+    for k in ("Q_raw", "dev_rho_L1", "dev_psi_L2"):
+        assert abs(m[k] - mo[k]) < 1e-10 * abs(mo[k]), k
+    plan.close()
+
+
 def test_adaptive_rejects_bad_arguments():
     from paper_2310_07119_amd.twa import TwError
-    p1 = Problem(n=(64,), n_real=2, n_tot=1e3)
-    plan = Plan(p1)
-    psi = torch.zeros((2, 64), dtype=torch.complex128, device="cuda")
-    with pytest.raises(TwError):
-        plan.step_adaptive(psi, 2, 1e-3)
     p2 = Problem(n=(32, 32), n_real=2, n_tot=1e3)
     plan2 = Plan(p2)
     psi2 = torch.zeros((2, 32, 32), dtype=torch.complex128, device="cuda")

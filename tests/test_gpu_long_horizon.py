@@ -90,18 +90,20 @@ def _fp32_against_fp64(name, seed):
 
 
 # Errors of the FP32 split form against FP64 at the end of each full run
-# (normwise over the whole output array; scalars relative). 2D, measured on
-# MI355X: mean_psi 1.08e-4, mean_rho 1.41e-4, var_rho 1.47e-4, norm 9.96e-5,
-# energy 1.0e-6, Q_raw 5.5e-7, dev_rho_L1 5.2e-7, dev_psi_L2 2.0e-7, classical
-# energy 1.12e-4: the FP32 fields lose 2e-8 of their norm per step, the same
-# for every field, which the realizations' energies (dominated by the
-# vacuum noise at high k) and Q barely see. The bounds are about twice the
-# measured values. 3D: every moment within the 1e-4 bar.
+# (normwise over the whole output array; scalars relative), measured on
+# MI355X:
+#   2D (5000 steps): mean_psi 2.4e-5, mean_rho 2.4e-5, var_rho 2.6e-5, norm
+#     2.0e-7, energy 1.4e-7, Q_raw 1.4e-8, dev_rho_L1 2.3e-7, dev_psi_L2 1.0e-6,
+#     classical energy 1.3e-6;
+#   3D (2000 steps): mean_psi 7.7e-6, mean_rho 1.0e-5, var_rho 8.8e-5, norm
+#     1.7e-7, energy 8.0e-8, Q_raw 1.6e-9, dev_rho_L1 6.0e-6, dev_psi_L2 7.2e-6,
+#     classical energy 7.3e-8.
+# The bounds are about twice these, and never above the FP32 bar of 1e-4.
 FP32_FULL_RUN_BOUNDS = {
-    "2d_n512_pair": {"mean_psi": 2.2e-4, "mean_rho": 2.8e-4, "var_rho": 3e-4, "norm": 2e-4, "energy": 2e-6,
-                     "Q_raw": 1.1e-6, "dev_rho_L1": 1.1e-6, "dev_psi_L2": 4e-7, "energy_classical": 2.2e-4},
-    "3d_n128_grf": {"mean_psi": 1e-4, "mean_rho": 1e-4, "var_rho": 1e-4, "norm": 1e-4, "energy": 1e-4,
-                    "Q_raw": 1e-4, "dev_rho_L1": 1e-4, "dev_psi_L2": 1e-4, "energy_classical": 1e-4},
+    "2d_n512_pair": {"mean_psi": 5e-5, "mean_rho": 5e-5, "var_rho": 5.5e-5, "norm": 4e-7, "energy": 3e-7,
+                     "Q_raw": 3e-8, "dev_rho_L1": 5e-7, "dev_psi_L2": 2e-6, "energy_classical": 2.5e-6},
+    "3d_n128_grf": {"mean_psi": 1.6e-5, "mean_rho": 2e-5, "var_rho": 1e-4, "norm": 3.5e-7, "energy": 1.6e-7,
+                    "Q_raw": 3.2e-9, "dev_rho_L1": 1.2e-5, "dev_psi_L2": 1.5e-5, "energy_classical": 1.5e-7},
 }
 
 
