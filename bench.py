@@ -17,6 +17,7 @@ Extra objects in the line:
   tracers       the same workload with test particles in every field
   resident_1d   the 1D workload (fields resident in one workgroup for all steps)
   diagnostics   tw_moments with every optional output
+  kgauss_512sq  the paper's momentum-space Gaussian problem at 512^2 (FP64, device-chosen steps)
   scale_512cube the paper's momentum-space Gaussian problem at 512^3 (FP32)
   batched       the three-size 3D soliton ensemble advanced from one HIP graph
   surrogate     the reduced FNO surrogate study
@@ -247,6 +248,42 @@ def run_adaptive(wl, precision, steps, warmup, seed=20231007, courant=0.5):
     return {"value": p.n_real * p.ncell * steps / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
             "courant": courant, "dt_max": dt_max, "dt_min_chosen": float(d.min()), "dt_max_chosen": float(d.max()),
             "simulated_time": float(d.sum()), "timed": "tw_step_adaptive only (no sampling or moments)"}
+
+
+def run_kgauss_2d(steps, seed=5, courant=0.5):
+    """The paper's 2D momentum-space Gaussian at its full size (512^2, 64
+    realizations + the classical field, FP64, physical units) with step sizes
+    chosen on the device (dt_max 10 Myr): sampling, steps, moments."""
+    import torch
+    from paper_2310_07119_amd import Plan, Problem, inputs
+
+    wl = dict(inputs.WORKLOADS["2d_n512_kgauss"])
+    p = Problem(n=wl["n"], box=wl["box"], hbar_m=wl["hbar_m"], G=wl["G"], m_tot=wl["m_tot"],
+                n_tot=wl["n_tot"], n_real=wl["n_real"], precision="fp64")
+    plan = Plan(p)
+    plan.autotune()
+    cl = torch.from_numpy(inputs.initial_field("2d_n512_kgauss")).cuda()
+    psi = plan.sample(cl, seed)
+    clt = cl.clone()
+    plan.step_adaptive(psi, 2, wl["dt"], courant, clt)      # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi = plan.sample(cl, seed, out=psi)
+    clt.copy_(cl)
+    dts = plan.step_adaptive(psi, steps, wl["dt"], courant, clt)
+    m = plan.moments(psi, clt, energy=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = dts.cpu()
+    out = {"workload": "2d_n512_kgauss", "grid": list(p.n), "n_real": p.n_real, "precision": "fp64",
+           "value": p.n_real * p.ncell * steps / el, "unit": METRIC, "ms_per_step": 1e3 * el / steps,
+           "steps": steps, "dt_myr_first": float(d[0]), "dt_myr_last": float(d[-1]),
+           "simulated_myr": float(d.sum()), "Q_raw": m["Q_raw"], "norm_mean": m["norm_mean"],
+           "timed": "tw_sample + tw_step_adaptive + tw_moments (with energies)"}
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_tracers(wl, precision, steps, warmup, ntracer=64, seed=20231007):
@@ -597,6 +634,7 @@ def main():
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--no-1d", dest="no_1d", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-kgauss", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -657,6 +695,9 @@ def main():
     if not args.no_diagnostics:
         out["diagnostics"] = run_diagnostics(wl, args.precision)
         log(f"diagnostics: {out['diagnostics']}")
+    if not args.no_kgauss:
+        out["kgauss_512sq"] = run_kgauss_2d(args.steps)
+        log(f"kgauss 512^2: {out['kgauss_512sq']}")
     if not args.no_scale:
         out["scale_512cube"] = run_scale(max(args.steps // 5, 2))
         log(f"scale: {out['scale_512cube']}")

@@ -339,8 +339,10 @@ int tw_fno_forward(tw_fno fno, const float* params, const float* x, int32_t batc
 int tw_fno_backward(tw_fno fno, const float* params, const float* x, int32_t batch, const float* dy, float* grads,
                     void* stream);
 
-/* loss[0] = mean((y - t)^2) over n values (FP64 sum), dy = 2 (y - t) / n (dy and
- * loss may be NULL). Device pointers. */
+/* loss[0] = mean((y - t)^2) over n values (FP64 sums in a fixed order), dy =
+ * 2 (y - t) / n (dy and loss may be NULL). Device pointers. The partial sums
+ * live in a small fixed device array of the library: calls that overlap on one
+ * GPU (two streams, two threads) race and must be ordered by the caller. */
 int tw_fno_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream);
 
 /* One bias-corrected Adam step (Kingma and Ba) over n parameters; step >= 1. */

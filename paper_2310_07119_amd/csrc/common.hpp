@@ -192,9 +192,18 @@ __device__ __forceinline__ cx<T> kick_rotate(cx<T> v, double arg) {
       case 3: w = {-v.im, v.re}; break;
       default: break;
     }
-    float s, cm1;
-    sincos_m1_series((float)r, s, cm1);
-    const float t = s * __builtin_amdgcn_rcpf(2.f + cm1);
+    float s, t;
+    if (fabs(r) <= 0.03125) {
+      // the common case (kick phases are small): sin x and tan(x/2) by their
+      // series, whose next terms are below 1e-12 relative for |x| <= 2^-5
+      const float x = (float)r, x2 = x * x;
+      s = x + x * x2 * (x2 * (1.f / 120.f) - 1.f / 6.f);
+      t = 0.5f * x + 0.5f * x * x2 * (x2 * (1.f / 120.f) + 1.f / 12.f);
+    } else {
+      float cm1;
+      sincos_m1_series((float)r, s, cm1);
+      t = s * __builtin_amdgcn_rcpf(2.f + cm1);
+    }
     // rotation by -r
     const float x1 = __builtin_fmaf(t, w.im, w.re);
     const float y1 = __builtin_fmaf(-s, x1, w.im);

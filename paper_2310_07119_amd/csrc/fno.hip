@@ -8,13 +8,15 @@
 // kx < mx (real half-spectrum) and ky in {0..my-1, H-my..H-1}, then a
 // projection C -> proj -> c_out with GELU in between. Every dense contraction
 // (pointwise layers, the four truncated DFT stages, weight gradients) runs on
-// the BF16 matrix-core GEMM; mode mixing, GELU, biases and reductions run in
-// FP32 (reductions FP64).
+// the BF16 matrix-core GEMM; the pointwise GEMMs add the bias and the
+// spectral branch and apply GELU (forward) or GELU' (backward) in their
+// epilogue, in FP32; mode mixing runs in FP32, reductions in FP64.
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <numeric>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fno_internal.hpp"
@@ -89,10 +91,25 @@ struct Fno {
 
 int64_t positions(const Fno& F, int batch) { return (int64_t)batch * F.cfg.H * F.cfg.W; }
 
+// Epilogue of a GEMM (GemmArgs): bias and added matrix, a second output with
+// GELU, or a GELU' factor (the fused pointwise layers).
+struct Epi {
+  const float* add = nullptr;
+  const float* bias = nullptr;
+  const float* gz = nullptr;
+  float* out2 = nullptr;
+  int act = 0;
+  int gz_into_c = 0;
+};
+
 hipError_t gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t sAm,
                 int64_t sAk, const float* B, int64_t sBk, int64_t sBn, float beta, float* C, int64_t sCm,
-                int64_t sCn, int64_t batch = 1, int64_t sAb = 0, int64_t sBb = 0, int64_t sCb = 0) {
+                int64_t sCn, int64_t batch = 1, int64_t sAb = 0, int64_t sBb = 0, int64_t sCb = 0,
+                const Epi& epi = Epi()) {
   GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.add = epi.add; g.bias = epi.bias; g.gz = epi.gz; g.out2 = epi.out2;
+  g.act = epi.act; g.gz_into_c = epi.gz_into_c;
   g.A = A; g.B = B; g.C = C;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.sAb = sAb; g.sAm = sAm; g.sAk = sAk;
@@ -323,9 +340,12 @@ int tw_fno_forward(tw_fno f, const float* params, const float* x, int32_t batch,
   const int64_t P = positions(F, batch), C = c.width, K2 = 2LL * c.modes_y, mx = c.modes_x;
   const int64_t PC = (int64_t)F.max_batch * c.H * c.W * C;  // per-layer stride of saved activations
   const int64_t bstride = (int64_t)F.max_batch * K2 * mx * C;
+  // every pointwise layer is one GEMM whose epilogue adds the bias (and the
+  // spectral branch) and writes the activation
   float* v0 = F.v;
-  FNO_HIP(gemm(s, P, C, c.c_in, 1.f, x, c.c_in, 1, params + L.lift_w, C, 1, 0.f, v0, C, 1));
-  FNO_HIP(launch_bias_act(v0, nullptr, params + L.lift_b, nullptr, P * C, (int)C, 0, s));
+  Epi lift;
+  lift.bias = params + L.lift_b;
+  FNO_HIP(gemm(s, P, C, c.c_in, 1.f, x, c.c_in, 1, params + L.lift_w, C, 1, 0.f, v0, C, 1, 1, 0, 0, 0, lift));
   for (int l = 0; l < c.layers; ++l) {
     float* vl = F.v + l * PC;
     float* vn = F.v + (l + 1) * PC;
@@ -333,14 +353,23 @@ int tw_fno_forward(tw_fno f, const float* params, const float* x, int32_t batch,
     float* br = F.bsav + (2 * l) * bstride;
     float* bi = F.bsav + (2 * l + 1) * bstride;
     if (int rc = spectral_fwd(F, s, batch, vl, params + L.Rre[l], params + L.Rim[l], br, bi, F.s)) return rc;
-    FNO_HIP(gemm(s, P, C, C, 1.f, vl, C, 1, params + L.W[l], C, 1, 0.f, ul, C, 1));
-    FNO_HIP(launch_bias_act(ul, F.s, params + L.b[l], vn, P * C, (int)C, l < c.layers - 1 ? 1 : 0, s));
+    Epi e;  // u_l = S(v_l) + v_l W_l + b_l, v_{l+1} = GELU(u_l) (u_l after the last layer)
+    e.add = F.s;
+    e.bias = params + L.b[l];
+    e.out2 = vn;
+    e.act = l < c.layers - 1 ? 1 : 0;
+    FNO_HIP(gemm(s, P, C, C, 1.f, vl, C, 1, params + L.W[l], C, 1, 0.f, ul, C, 1, 1, 0, 0, 0, e));
   }
   const float* vL = F.v + (int64_t)c.layers * PC;
-  FNO_HIP(gemm(s, P, c.proj, C, 1.f, vL, C, 1, params + L.q1_w, c.proj, 1, 0.f, F.z1, c.proj, 1));
-  FNO_HIP(launch_bias_act(F.z1, nullptr, params + L.q1_b, F.h, P * c.proj, c.proj, 1, s));
-  FNO_HIP(gemm(s, P, c.c_out, c.proj, 1.f, F.h, c.proj, 1, params + L.q2_w, c.c_out, 1, 0.f, y, c.c_out, 1));
-  FNO_HIP(launch_bias_act(y, nullptr, params + L.q2_b, nullptr, P * c.c_out, c.c_out, 0, s));
+  Epi e1;
+  e1.bias = params + L.q1_b;
+  e1.out2 = F.h;
+  e1.act = 1;
+  FNO_HIP(gemm(s, P, c.proj, C, 1.f, vL, C, 1, params + L.q1_w, c.proj, 1, 0.f, F.z1, c.proj, 1, 1, 0, 0, 0, e1));
+  Epi e2;
+  e2.bias = params + L.q2_b;
+  FNO_HIP(gemm(s, P, c.c_out, c.proj, 1.f, F.h, c.proj, 1, params + L.q2_w, c.c_out, 1, 0.f, y, c.c_out, 1, 1, 0, 0,
+               0, e2));
   return TW_OK;
 }
 
@@ -358,23 +387,27 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
   // projection 2
   FNO_HIP(weight_grad(F, s, P, c.proj, c.c_out, F.h, dy, grads + L.q2_w));
   FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, F.parts, F.parts_len, F.parts2, s));
-  FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1));
-  FNO_HIP(launch_gelu_back(F.dz, F.z1, F.dz, P * c.proj, s));
+  Epi eg;  // dz = (dy q2_w^T) GELU'(z1)
+  eg.gz = F.z1;
+  eg.gz_into_c = 1;
+  FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1, 1, 0, 0,
+               0, eg));
   // projection 1
   const float* vL = F.v + (int64_t)c.layers * PC;
   FNO_HIP(weight_grad(F, s, P, C, c.proj, vL, F.dz, grads + L.q1_w));
   FNO_HIP(launch_colsum(F.dz, P, c.proj, grads + L.q1_b, 0, F.parts, F.parts_len, F.parts2, s));
+  // dv: gradient of the layer input v_l; du: of u_l. No activation follows the
+  // last layer (du = dv there); before every other layer's gradient, the
+  // data-gradient GEMM of the layer above also writes du = dv GELU'(u) in its
+  // epilogue, into the buffer the current du does not occupy (F.s, free in the
+  // backward pass, and F.t2 in turn)
   float* dv = F.t1;
   float* du = F.t2;
+  float* du_next = F.s;
   FNO_HIP(gemm(s, P, C, c.proj, 1.f, F.dz, c.proj, 1, params + L.q1_w, 1, c.proj, 0.f, dv, C, 1));
+  FNO_HIP(hipMemcpyAsync(du, dv, sizeof(float) * P * C, hipMemcpyDeviceToDevice, s));
   for (int l = c.layers - 1; l >= 0; --l) {
     const float* vl = F.v + l * PC;
-    const float* ul = F.u + l * PC;
-    if (l < c.layers - 1) {
-      FNO_HIP(launch_gelu_back(dv, ul, du, P * C, s));
-    } else {
-      FNO_HIP(hipMemcpyAsync(du, dv, sizeof(float) * P * C, hipMemcpyDeviceToDevice, s));
-    }
     FNO_HIP(weight_grad(F, s, P, C, C, vl, du, grads + L.W[l]));
     FNO_HIP(launch_colsum(du, P, (int)C, grads + L.b[l], 0, F.parts, F.parts_len, F.parts2, s));
     const float* br = F.bsav + (2 * l) * bstride;
@@ -382,7 +415,13 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
     if (int rc = spectral_bwd(F, s, batch, du, br, bi, params + L.Rre[l], params + L.Rim[l], grads + L.Rre[l],
                               grads + L.Rim[l], dv))
       return rc;
-    FNO_HIP(gemm(s, P, C, C, 1.f, du, C, 1, params + L.W[l], 1, C, 1.f, dv, C, 1));
+    Epi eb;
+    if (l > 0) {
+      eb.gz = F.u + (l - 1) * PC;
+      eb.out2 = du_next;
+    }
+    FNO_HIP(gemm(s, P, C, C, 1.f, du, C, 1, params + L.W[l], 1, C, 1.f, dv, C, 1, 1, 0, 0, 0, eb));
+    std::swap(du, du_next);
   }
   FNO_HIP(weight_grad(F, s, P, c.c_in, C, x, dv, grads + L.lift_w));
   FNO_HIP(launch_colsum(dv, P, (int)C, grads + L.lift_b, 0, F.parts, F.parts_len, F.parts2, s));

@@ -16,12 +16,21 @@ struct GemmArgs {
   int64_t sBb, sBk, sBn;
   int64_t sCb, sCm, sCn;
   float alpha, beta;
+  // Epilogue, applied to r = beta C + alpha A B (all optional): r += add[b, m, n]
+  // (same strides as C) and r += bias[n]; with gz, g = r GELU'(gz[b, m, n])
+  // replaces r in C if gz_into_c; out2[b, m, n] (strides of C) receives g
+  // with gz, else GELU(r) if act, else r.
+  const float* add;
+  const float* bias;
+  const float* gz;
+  float* out2;
+  int32_t act;
+  int32_t gz_into_c;
+  int32_t a_vec;    // set by launch_gemm: A staged with four-element loads
+  int32_t row_epi;  // set by launch_gemm: width-32 tiles write the epilogue as whole rows through LDS
 };
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
-hipError_t launch_bias_act(float* u, const float* s, const float* bias, float* v, int64_t n, int C, int act,
-                           hipStream_t st);
-hipError_t launch_gelu_back(const float* g, const float* z, float* d, int64_t n, hipStream_t st);
 hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, float* parts,
                          int64_t parts_len, double* tmp, hipStream_t st);
 hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st,

@@ -1,5 +1,6 @@
 // Kernels of the Fourier-neural-operator surrogate: a strided batched GEMM on
-// BF16 matrix cores (FP32 accumulate), spectral mode mixing, GELU, bias,
+// BF16 matrix cores (FP32 accumulate) whose epilogue applies the pointwise
+// layers' bias, spectral-branch sum, GELU or GELU', spectral mode mixing,
 // reductions, MSE loss and Adam.
 //
 // GEMM: C[b] = beta C[b] + alpha A[b] B[b] with FP32 storage; both operands are
@@ -27,6 +28,11 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
   return (unsigned short)(r >> 16);
 }
 
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
 constexpr int GK = 32;        // K per stage (one MFMA)
 constexpr int GLD = GK + 8;   // LDS row pitch in bf16 (16-byte pad)
 
@@ -34,20 +40,27 @@ constexpr int GLD = GK + 8;   // LDS row pitch in bf16 (16-byte pad)
 // owns a 32 x 32 sub-tile (2 x 2 MFMA blocks of 16 x 16). TM x TN is 64 x 64,
 // or 128 x 32 for the skinny products (N <= 32: the pointwise layers), where
 // a square tile would leave half of its wavefronts on zero columns.
-template <int TM, int TN>
+// AVEC: A rows K-contiguous and 16-byte aligned (four-element loads); ROWEPI:
+// width-32 tile with the row-wise epilogue through LDS (both chosen at launch).
+template <int TM, int TN, bool AVEC, bool ROWEPI>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   static_assert(TM * TN == 4096 && TM % 32 == 0 && TN % 32 == 0, "four 32x32 wavefront tiles");
   constexpr int WN = TN / 32;  // wavefronts along n
   constexpr int EA = TM * GK / 256, EB = TN * GK / 256;  // staged elements per thread
-  __shared__ __align__(16) unsigned short As[TM * GLD];  // [m][k]
-  __shared__ __align__(16) unsigned short Bs[TN * GLD];  // [n][k]  (B transposed)
+  // operand staging (BF16), reused after the k-loop for the output tile of
+  // the row-wise epilogue (FP32, pitch CP)
+  constexpr int CP = TN + 4;
+  constexpr size_t AB_BYTES = (size_t)(TM + TN) * GLD * sizeof(unsigned short);
+  constexpr size_t C_BYTES = (size_t)TM * CP * sizeof(float);
+  __shared__ __align__(16) unsigned char smem[AB_BYTES > C_BYTES ? AB_BYTES : C_BYTES];
+  unsigned short* As = reinterpret_cast<unsigned short*>(smem);  // [m][k]
+  unsigned short* Bs = As + TM * GLD;                            // [n][k]  (B transposed)
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int64_t b = blockIdx.z;
   const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
   const float* __restrict__ A = g.A + b * g.sAb;
   const float* __restrict__ B = g.B + b * g.sBb;
-  float* __restrict__ C = g.C + b * g.sCb;
   const int wm = (w / WN) * 32, wn = (w % WN) * 32;
 
   f32x4 acc[2][2];
@@ -60,15 +73,31 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   // when it has one
   const bool a_k_fast = g.sAk == 1;
   const bool b_n_fast = g.sBn == 1;
+  constexpr bool a_vec = AVEC;
   for (int64_t k0 = 0; k0 < g.K; k0 += GK) {
     float va[EA], vb[EB];
+    if constexpr (a_vec) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {  // issue every load of the stage before converting
-      const int idx = tid + 256 * e;
-      const int mm = a_k_fast ? idx / GK : idx % TM;
-      const int kk = a_k_fast ? idx % GK : idx / TM;
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      va[e] = (gm < g.M && gk < g.K) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
+      for (int e = 0; e < EA / 4; ++e) {
+        const int idx = tid + 256 * e;
+        const int mm = idx / (GK / 4), kq = (idx % (GK / 4)) * 4;
+        const int64_t gm = m0 + mm, gk = k0 + kq;
+        const float4 q = (gm < g.M && gk < g.K) ? *reinterpret_cast<const float4*>(A + gm * g.sAm + gk)
+                                                 : float4{0.f, 0.f, 0.f, 0.f};
+        va[4 * e] = q.x;
+        va[4 * e + 1] = q.y;
+        va[4 * e + 2] = q.z;
+        va[4 * e + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {  // issue every load of the stage before converting
+        const int idx = tid + 256 * e;
+        const int mm = a_k_fast ? idx / GK : idx % TM;
+        const int kk = a_k_fast ? idx % GK : idx / TM;
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        va[e] = (gm < g.M && gk < g.K) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
+      }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -78,12 +107,23 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       const int64_t gn = n0 + nn, gk = k0 + kk;
       vb[e] = (gn < g.N && gk < g.K) ? B[gk * g.sBk + gn * g.sBn] : 0.f;
     }
+    if constexpr (a_vec) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = tid + 256 * e;
-      const int mm = a_k_fast ? idx / GK : idx % TM;
-      const int kk = a_k_fast ? idx % GK : idx / TM;
-      As[mm * GLD + kk] = f32_to_bf16_rne(va[e]);
+      for (int e = 0; e < EA / 4; ++e) {
+        const int idx = tid + 256 * e;
+        const int mm = idx / (GK / 4), kq = (idx % (GK / 4)) * 4;
+        const uint32_t lo = f32_to_bf16_rne(va[4 * e]) | ((uint32_t)f32_to_bf16_rne(va[4 * e + 1]) << 16);
+        const uint32_t hi = f32_to_bf16_rne(va[4 * e + 2]) | ((uint32_t)f32_to_bf16_rne(va[4 * e + 3]) << 16);
+        *reinterpret_cast<uint2*>(&As[mm * GLD + kq]) = uint2{lo, hi};
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        const int idx = tid + 256 * e;
+        const int mm = a_k_fast ? idx / GK : idx % TM;
+        const int kk = a_k_fast ? idx % GK : idx / TM;
+        As[mm * GLD + kk] = f32_to_bf16_rne(va[e]);
+      }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -107,6 +147,54 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   }
   // output block (i, j): lane holds column (lane & 15), rows 4 (lane >> 4) + q
   const int col = lane & 15, rb = (lane >> 4) * 4;
+  if constexpr (ROWEPI) {
+    static_assert(TN == 32, "the row-wise epilogue moves 32-float rows");
+    {
+      // the tile goes through LDS so that the epilogue reads and writes whole
+      // 128-byte rows (eight threads of 16 bytes per row; the MFMA layout
+      // gives 64-byte pieces of four rows per instruction)
+      float* Cs = reinterpret_cast<float*>(smem);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Cs[(wm + 16 * i + rb + q) * CP + wn + 16 * j + col] = acc[i][j][q];
+      __syncthreads();
+      const int c4 = (tid & 7) * 4;
+#pragma unroll 1
+      for (int pr = 0; pr < TM / 32; ++pr) {
+        const int r = pr * 32 + (tid >> 3);
+        const int64_t gm = m0 + r, gn = n0 + c4;
+        if (gm >= g.M || gn >= g.N) continue;  // N % 4 == 0: a piece is all in or all out
+        const int64_t off = b * g.sCb + gm * g.sCm + gn;
+        const float4 a4 = *reinterpret_cast<const float4*>(&Cs[r * CP + c4]);
+        const float zero4[4] = {0.f, 0.f, 0.f, 0.f};
+        float av[4] = {a4.x, a4.y, a4.z, a4.w}, pv[4], dv[4], bv[4], zv[4];
+        auto ld4 = [&](const float* src, float (&dst)[4]) {
+          const float4 v = *reinterpret_cast<const float4*>(src);
+          dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+        };
+        if (g.beta != 0.f) ld4(g.C + off, pv); else for (int e = 0; e < 4; ++e) pv[e] = zero4[e];
+        if (g.add) ld4(g.add + off, dv);
+        if (g.bias) ld4(g.bias + gn, bv);
+        if (g.gz) ld4(g.gz + off, zv);
+        float cv[4], ov[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float rr = g.beta * pv[e] + g.alpha * av[e];
+          if (g.add) rr += dv[e];
+          if (g.bias) rr += bv[e];
+          const float gr = g.gz ? rr * gelu_grad_f(zv[e]) : rr;
+          cv[e] = g.gz_into_c ? gr : rr;
+          ov[e] = g.gz ? gr : (g.act ? gelu_f(rr) : rr);
+        }
+        *reinterpret_cast<float4*>(g.C + off) = float4{cv[0], cv[1], cv[2], cv[3]};
+        if (g.out2) *reinterpret_cast<float4*>(g.out2 + off) = float4{ov[0], ov[1], ov[2], ov[3]};
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -115,61 +203,43 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       for (int q = 0; q < 4; ++q) {
         const int64_t gm = m0 + wm + 16 * i + rb + q, gn = n0 + wn + 16 * j + col;
         if (gm < g.M && gn < g.N) {
-          float* p = C + gm * g.sCm + gn * g.sCn;
+          const int64_t off = b * g.sCb + gm * g.sCm + gn * g.sCn;
+          float* p = g.C + off;
           const float prev = g.beta != 0.f ? *p : 0.f;
-          *p = g.beta * prev + g.alpha * acc[i][j][q];
+          float r = g.beta * prev + g.alpha * acc[i][j][q];
+          if (g.add) r += g.add[off];
+          if (g.bias) r += g.bias[gn];
+          const float gr = g.gz ? r * gelu_grad_f(g.gz[off]) : r;
+          *p = g.gz_into_c ? gr : r;
+          if (g.out2) g.out2[off] = g.gz ? gr : (g.act ? gelu_f(r) : r);
         }
       }
 }
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (g.batch > 65535) return hipErrorInvalidValue;
+hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return hipSuccess;
+  if (g0.batch > 65535) return hipErrorInvalidValue;
+  GemmArgs g = g0;
+  auto al16 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  g.a_vec = g.sAk == 1 && g.sAm % 4 == 0 && g.sAb % 4 == 0 && g.K % 4 == 0 && al16(g.A);
+  g.row_epi = g.N <= 32 && g.sCn == 1 && g.sCm % 4 == 0 && g.sCb % 4 == 0 && g.N % 4 == 0 && al16(g.C) &&
+              (!g.add || al16(g.add)) && (!g.bias || al16(g.bias)) && (!g.gz || al16(g.gz)) &&
+              (!g.out2 || al16(g.out2));
   if (g.N <= 32) {
     dim3 grid((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 127) / 128), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_bf16_kernel<128, 32>), grid, dim3(256), 0, s, g);
+    if (g.a_vec && g.row_epi) hipLaunchKernelGGL((gemm_bf16_kernel<128, 32, true, true>), grid, dim3(256), 0, s, g);
+    else if (g.a_vec) hipLaunchKernelGGL((gemm_bf16_kernel<128, 32, true, false>), grid, dim3(256), 0, s, g);
+    else if (g.row_epi) hipLaunchKernelGGL((gemm_bf16_kernel<128, 32, false, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_bf16_kernel<128, 32, false, false>), grid, dim3(256), 0, s, g);
   } else {
     dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_bf16_kernel<64, 64>), grid, dim3(256), 0, s, g);
+    if (g.a_vec) hipLaunchKernelGGL((gemm_bf16_kernel<64, 64, true, false>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_bf16_kernel<64, 64, false, false>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- elementwise
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
-}
-
-// u[p, c] += s[p, c] (if s) + bias[c];  v = act ? GELU(u) : u (v may alias u when !act)
-__global__ void bias_act_kernel(float* __restrict__ u, const float* __restrict__ s, const float* __restrict__ bias,
-                                float* __restrict__ v, int64_t n, int C, int act) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float x = u[i] + (s ? s[i] : 0.f) + bias[i % C];
-  u[i] = x;
-  if (v) v[i] = act ? gelu_f(x) : x;
-}
-
-hipError_t launch_bias_act(float* u, const float* s, const float* bias, float* v, int64_t n, int C, int act,
-                           hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bias_act_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, s, bias, v, n, C, act);
-  return hipGetLastError();
-}
-
-// d[i] = g[i] * GELU'(z[i])
-__global__ void gelu_back_kernel(const float* __restrict__ g, const float* __restrict__ z, float* __restrict__ d,
-                                 int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = g[i] * gelu_grad_f(z[i]);
-}
-
-hipError_t launch_gelu_back(const float* g, const float* z, float* d, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gelu_back_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, z, d, n);
-  return hipGetLastError();
-}
 
 // out[c] (+)= sum over rows p < P of x[p, c]; one workgroup per column block,
 // FP64 accumulation, fixed order (deterministic).
@@ -358,48 +428,50 @@ hipError_t launch_modemix_bwd(const float* br, const float* bi, const float* dcr
 }
 
 // --------------------------------------------------------------- training
-// loss = (1/n) sum (y - t)^2 (one workgroup, FP64, written to loss[0]); dy = 2 (y - t) / n
-// Mean squared error and its gradient. One workgroup of 1024 threads so the
-// loss is reduced in a fixed order without a workspace; four independent
-// elements per thread per iteration keep enough loads in flight.
-__global__ void __launch_bounds__(1024) mse_kernel(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
-                                                   float* __restrict__ dy, float* __restrict__ loss) {
-  __shared__ double red[1024];
-  const int tid = threadIdx.x;
-  double s = 0.0;
+// Mean squared error loss = (1/n) sum (y - t)^2 (FP64 sums, written to
+// loss[0]) and its gradient dy = 2 (y - t) / n, in two launches: up to
+// kMseParts workgroups each sum a contiguous chunk into a fixed device array,
+// then one thread adds the partial sums in order (deterministic). The array
+// belongs to this file's kernels; MSE calls that overlap on one GPU share it
+// and must be ordered by the caller.
+constexpr int kMseParts = 512;
+__device__ double g_mse_parts[kMseParts];
+
+__global__ void __launch_bounds__(256) mse_parts_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                        int64_t n, int64_t chunk, float* __restrict__ dy) {
+  __shared__ double red[4];
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
   const double inv = 1.0 / (double)n;
-  constexpr int U = 4;
-  int64_t i = tid;
-  for (; i + (U - 1) * 1024 < n; i += U * 1024) {
-    float yv[U], tv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      yv[u] = y[i + u * 1024];
-      tv[u] = t[i + u * 1024];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double d = (double)yv[u] - (double)tv[u];
-      s += d * d;
-      if (dy) dy[i + u * 1024] = (float)(2.0 * d * inv);
-    }
-  }
-  for (; i < n; i += 1024) {
+  double s = 0.0;
+#pragma unroll 4
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     const double d = (double)y[i] - (double)t[i];
     s += d * d;
     if (dy) dy[i] = (float)(2.0 * d * inv);
   }
-  red[tid] = s;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
-  if (tid == 0 && loss) loss[0] = (float)(red[0] * inv);
+  if (threadIdx.x == 0) g_mse_parts[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// One wavefront: lane l sums parts l, l + 64, ... in order, then a fixed
+// butterfly combines the lanes (the same order on every call).
+__global__ void __launch_bounds__(64) mse_finish_kernel(int nb, int64_t n, float* __restrict__ loss) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) s += g_mse_parts[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0 && loss) loss[0] = (float)(s / (double)n);
 }
 
 hipError_t launch_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, y, t, n, dy, loss);
+  int64_t nb = (n + 4095) / 4096;  // at least 4096 elements per workgroup
+  if (nb > kMseParts) nb = kMseParts;
+  if (nb < 1) nb = 1;
+  const int64_t chunk = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(mse_parts_kernel, dim3((unsigned)nb), dim3(256), 0, st, y, t, n, chunk, dy);
+  hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(64), 0, st, (int)nb, n, loss);
   return hipGetLastError();
 }
 

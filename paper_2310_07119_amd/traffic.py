@@ -43,8 +43,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # compiled kernel names (pass_kernel<T, N, MODE, ROWS> / cols_kernel<T, N, MODE>)
 KIND_MODES = {"pass_drift": 0, "pass_drift_rho": 1, "pass_zfwd": 2, "pass_zpoisson": 3, "pass_zinv": 4,
               "pass_kick_drift": 5, "pass_rho": 6, "pass_kin_sum": 7, "pass_pot_sum": 8}
+# xy-plane passes of D = 3 (slab_kernel<T, N, MODE>)
+SLAB_MODES = {"pass_slab_drift": 0, "pass_slab_drift_rho": 1, "pass_slab_poisson": 2, "pass_slab_kick_drift": 3}
 SOURCES = ("csrc/fft.hpp", "csrc/common.hpp", "csrc/pass_common.hpp", "csrc/pass_rows.hpp", "csrc/pass_cols.hpp",
-           "csrc/kernels_step.hip", "csrc/kernels_cols.hip")
+           "csrc/kernels_step.hip", "csrc/kernels_cols.hip", "csrc/kernels_slab.hip")
 
 
 def source_digest():
@@ -81,8 +83,12 @@ def _per_dispatch(rows, counter, match):
 
 def summarize(a):
     ctype = "double" if a.precision == "fp64" else "float"
-    tag = f"<{ctype}, {a.length}, {KIND_MODES[a.kind]}"
-    match = lambda n: ("pass_kernel" in n or "cols_kernel" in n) and tag in n
+    if a.kind in SLAB_MODES:
+        tag = f"slab_kernel<{ctype}, {a.length}, {SLAB_MODES[a.kind]}>"
+        match = lambda n: tag in n
+    else:
+        tag = f"<{ctype}, {a.length}, {KIND_MODES[a.kind]}"
+        match = lambda n: ("pass_kernel" in n or "cols_kernel" in n) and tag in n
     fetch = _per_dispatch(_rows(a.fetch), "FETCH_SIZE", match)
     write = _per_dispatch(_rows(a.write), "WRITE_SIZE", match)
     copy_match = lambda n: "copy" in n.lower() or "elementwise" in n.lower()
@@ -118,16 +124,18 @@ def summarize(a):
     print(json.dumps(out))
 
 
+MODE_KIND = {m: k for k, m in KIND_MODES.items()}
+SLAB_KIND = {m: k for k, m in SLAB_MODES.items()}
+
+
 def _kind_of(name):
-    """(precision, mode) of a pass kernel from its compiled name, else None."""
+    """(precision, kernel kind) of a pass kernel from its compiled name, else None."""
     import re
-    m = re.search(r"(pass|cols)_kernel<(double|float), (\d+), (\d+)", name)
+    m = re.search(r"(pass|cols|slab)_kernel<(double|float), (\d+), (\d+)", name)
     if not m:
         return None
-    return ("fp64" if m.group(2) == "double" else "fp32"), int(m.group(4))
-
-
-MODE_KIND = {m: k for k, m in KIND_MODES.items()}
+    kinds = SLAB_KIND if m.group(1) == "slab" else MODE_KIND
+    return ("fp64" if m.group(2) == "double" else "fp32"), kinds[int(m.group(4))]
 
 
 def kernels(a):
@@ -151,7 +159,7 @@ def kernels(a):
             if k is None:
                 continue
             dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-            kinds.setdefault((k[0], MODE_KIND[k[1]]), []).append((r["Kernel_Name"], dur))
+            kinds.setdefault(k, []).append((r["Kernel_Name"], dur))
         bench = {}
         if a.bench_log:
             for ln in open(a.bench_log):
@@ -208,9 +216,10 @@ def counters(a):
     lines += a.commands.splitlines() + ["```", ""]
     lines += ["Per dispatch, averaged over the dispatches of each kernel; derived figures as rocprofv3 defines them",
               f"(CU_NUM = {a.cus}, GRBM_GUI_ACTIVE summed over {a.xcds} XCDs).", ""]
-    names = sorted({r["Kernel_Name"] for r in rows if "pass_kernel" in r["Kernel_Name"] or "cols_kernel" in r["Kernel_Name"]})
+    names = sorted({r["Kernel_Name"] for r in rows if _kind_of(r["Kernel_Name"])})
     names = [n for n in names if f"<{ctype}, {a.length}," in n]
-    table = ["| kernel | kind | dispatches | VALU busy | FP64 FLOP/s (TFLOP/s) | LDS active | LDS bank-conflict cycles | conflicts per LDS access |",
+    fp = "F64" if a.precision == "fp64" else "F32"
+    table = [f"| kernel | kind | dispatches | VALU busy | {fp} FLOP/s (TFLOP/s) | LDS active | LDS bank-conflict cycles | conflicts per LDS access |",
              "|---|---|---:|---:|---:|---:|---:|---:|"]
     for n in names:
         mode = int(n.split(",")[2].split(">")[0].strip())
@@ -228,21 +237,22 @@ def counters(a):
         lds = vals.get("SQ_LDS_IDX_ACTIVE")
         conf = vals.get("SQ_LDS_BANK_CONFLICT")
         fl = None
-        if all(k in vals for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")):
-            fl = 64 * (vals["SQ_INSTS_VALU_ADD_F64"] + vals["SQ_INSTS_VALU_MUL_F64"] + 2 * vals["SQ_INSTS_VALU_FMA_F64"])
+        if all(f"SQ_INSTS_VALU_{op}_{fp}" in vals for op in ("ADD", "MUL", "FMA")):
+            fl = 64 * (vals[f"SQ_INSTS_VALU_ADD_{fp}"] + vals[f"SQ_INSTS_VALU_MUL_{fp}"] + 2 * vals[f"SQ_INSTS_VALU_FMA_{fp}"])
         durs = {}
         for r in rows:
             if r["Kernel_Name"] == n:
                 durs[r.get("Dispatch_Id")] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
         dur_s = sum(durs.values()) / len(durs)
         f = lambda x, pct=True: "-" if x is None else (f"{100 * x:.1f}%" if pct else f"{x:.2f}")
-        table.append(f"| `{n[:52]}` | {MODE_KIND.get(mode, mode)} | {int(len(_per_dispatch(rows, 'GRBM_GUI_ACTIVE', lambda k, n=n: k == n)))} | "
+        table.append(f"| `{n[:52]}` | {(_kind_of(n) or (None, mode))[1]} | {int(len(_per_dispatch(rows, 'GRBM_GUI_ACTIVE', lambda k, n=n: k == n)))} | "
                      f"{f(valu / cyc if valu else None)} | {f(fl / dur_s / 1e12 if fl else None, False)} | "
                      f"{f(lds / cyc if lds else None)} | {f(conf / cyc if conf else None)} | "
                      f"{f(conf / (lds - conf) if (lds and conf) else None, False)} |")
     lines += table
-    lines += ["", "FLOP/s: 64 lanes x (ADD_F64 + MUL_F64 + 2 FMA_F64) instructions over the dispatch's own "
-              "duration (its end minus start timestamp in the counter run); FP64 vector peak 78.6 TFLOP/s.", ""]
+    peak = "FP64 vector peak 78.6" if fp == "F64" else "FP32 vector peak 157.3"
+    lines += ["", f"FLOP/s: 64 lanes x (ADD_{fp} + MUL_{fp} + 2 FMA_{fp}) instructions over the dispatch's own "
+              f"duration (its end minus start timestamp in the counter run); {peak} TFLOP/s.", ""]
     raw = ["| kernel | " + " | ".join(c.replace("SQ_", "").replace("GRBM_", "") for c in a.raw) + " |",
            "|---|" + "---:|" * len(a.raw)]
     for n in names:

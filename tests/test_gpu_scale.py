@@ -118,3 +118,35 @@ def test_largest_ensemble_per_sample_call():
     with pytest.raises(TwError):
         plan2.sample(cl, seed)
     plan2.close()
+
+
+def test_kgauss_512sq_full_grid_vs_oracle():
+    """The paper's 2D momentum-space Gaussian (Sec. "Momentum space gaussian",
+    Eq. (kspaceGauss)) on its full 512^2 grid in physical units (L = 60 kpc,
+    M_tot = 6e9 M_sun, hbar/m = 0.02 kpc^2/Myr), FP64, 8 realizations + the
+    classical field, 10 device-chosen steps against the oracle's adaptive
+    evolution of the same draws: step sizes, fields and moments at 1e-10."""
+    p, w = _problem("2d_n512_kgauss", "fp64", n_real=8)
+    psi_cl = inputs.initial_field("2d_n512_kgauss")
+    print("512^2 momentum-space Gaussian, 8 realizations, fp64, 10 adaptive steps", flush=True)
+    plan = Plan(p)
+    cl = torch.from_numpy(psi_cl).cuda()
+    psi = plan.sample(cl, 17)
+    clt = cl.clone()
+    psi0 = psi.cpu().numpy()
+    nsteps = 10
+    dts = plan.step_adaptive(psi, nsteps, w["dt"], courant=0.5, psi_classical=clt).cpu().numpy()
+    m = plan.moments(psi, clt)
+    torch.cuda.synchronize()
+    prob = oracle_problem(p)
+    ref, rdts = tw.evolve_adaptive(prob, np.concatenate([psi0, psi_cl[None]]), nsteps, w["dt"], 0.5)
+    assert rel(dts, rdts) < 1e-12
+    assert rel(psi.cpu().numpy(), ref[:-1]) < TOL["fp64"]
+    assert rel(clt.cpu().numpy(), ref[-1]) < TOL["fp64"]
+    mo = tw.moments(prob, ref[:-1], p.n_tot, ref[-1])
+    for k in ("mean_psi", "mean_rho", "var_rho", "norm", "energy"):
+        assert rel(m[k].cpu().numpy(), mo[k]) < TOL["fp64"], k
+    assert abs(m["Q_raw"] - mo["Q_raw"]) < TOL["fp64"] * abs(mo["Q_raw"])
+    plan.close()
+    del psi, clt
+    torch.cuda.empty_cache()
