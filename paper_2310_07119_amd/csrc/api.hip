@@ -529,6 +529,10 @@ int tw_plan_create(const tw_problem* pr, tw_plan* out) {
       vol = vol * pr->box[d];
     }
   }
+  if (P->ncell > (int64_t)INT32_MAX) {  // the pass kernels index cells of a field with 32-bit integers
+    delete P;
+    return fail(TW_EINVAL, "a field may hold at most 2^31 - 1 cells");
+  }
   P->dV = dv;
   P->volume = vol;
   P->fp32 = pr->precision == TW_FP32_SPLIT;

@@ -171,6 +171,17 @@ __device__ __forceinline__ void sincos_m1_series(float x, float& s, float& cm1) 
   cm1 = x2 * pc;
 }
 
+// Rotation of w by -x for |x| <= 2^-5 as the three shears above, with sin x
+// and tan(x/2) from their series (the next terms are below 1e-12 relative).
+__device__ __forceinline__ cx<float> rotate_small(cx<float> w, float x) {
+  const float x2 = x * x, xx2 = x * x2;
+  const float s = __builtin_fmaf(xx2, __builtin_fmaf(x2, 1.f / 120.f, -1.f / 6.f), x);
+  const float t = __builtin_fmaf(0.5f * xx2, __builtin_fmaf(x2, 1.f / 120.f, 1.f / 12.f), 0.5f * x);
+  const float x1 = __builtin_fmaf(t, w.im, w.re);
+  const float y1 = __builtin_fmaf(-s, x1, w.im);
+  return {__builtin_fmaf(t, y1, x1), y1};
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> kick_rotate(cx<T> v, double arg) {
   if constexpr (sizeof(T) == 8) {
@@ -192,23 +203,65 @@ __device__ __forceinline__ cx<T> kick_rotate(cx<T> v, double arg) {
       case 3: w = {-v.im, v.re}; break;
       default: break;
     }
-    float s, t;
-    if (fabs(r) <= 0.03125) {
-      // the common case (kick phases are small): sin x and tan(x/2) by their
-      // series, whose next terms are below 1e-12 relative for |x| <= 2^-5
-      const float x = (float)r, x2 = x * x;
-      s = x + x * x2 * (x2 * (1.f / 120.f) - 1.f / 6.f);
-      t = 0.5f * x + 0.5f * x * x2 * (x2 * (1.f / 120.f) + 1.f / 12.f);
-    } else {
-      float cm1;
-      sincos_m1_series((float)r, s, cm1);
-      t = s * __builtin_amdgcn_rcpf(2.f + cm1);
-    }
+    if (fabs(r) <= 0.03125) return rotate_small(w, (float)r);
+    float s, cm1;
+    sincos_m1_series((float)r, s, cm1);
+    const float t = s * __builtin_amdgcn_rcpf(2.f + cm1);
     // rotation by -r
     const float x1 = __builtin_fmaf(t, w.im, w.re);
     const float y1 = __builtin_fmaf(-s, x1, w.im);
     const float x2 = __builtin_fmaf(t, y1, x1);
     return {x2, y1};
+  }
+}
+
+// The kick of one field's R values held by a thread, v_m <- v_m exp(-i kick V_m),
+// with V_m the real (im = false) or imaginary part of the pair-packed
+// potential pot[m]. FP64: kick_rotate of each value. FP32: the phases are
+// formed in FP32 with the kick factor split into two floats (kick = k_hi +
+// k_lo, so the phase carries one rounding and no bias from rounding the kick
+// factor); when all R lie within 2^-5 (kick phases are small) each value
+// takes rotate_small, otherwise each takes kick_rotate with its FP64 phase.
+// One branch per field instead of one per value.
+template <class T, int R>
+__device__ __forceinline__ void kick_values(cx<T> (&v)[R], const cx<T> (&pot)[R], bool im, double kick) {
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], kick * (im ? pot[m].im : pot[m].re));
+  } else {
+    const float kh = (float)kick, kl = (float)(kick - (double)kh);
+    float x[R];
+    bool small = true;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const float p = im ? pot[m].im : pot[m].re;
+      x[m] = __builtin_fmaf(kh, p, kl * p);
+      small = small && fabsf(x[m]) <= 0.03125f;
+    }
+    if (small) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = rotate_small(v[m], x[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], kick * (double)(im ? pot[m].im : pot[m].re));
+    }
+  }
+}
+
+// Green's function factor of the Poisson solve at |k|^2 = k2 (zero mode
+// removed), -4 pi G / (|k|^2 N) with green = -4 pi G / N, in FP64 (applied with
+// mul_d). FP64 passes divide; FP32 passes take the hardware reciprocal
+// estimate refined by two Newton steps, exact far below FP32 resolution (a
+// per-mode error of FP32 size would bias the potential the same way every step).
+template <class T>
+__device__ __forceinline__ double green_factor(double k2, double green) {
+  if constexpr (sizeof(T) == 8) {
+    return (k2 == 0.0) ? 0.0 : green / k2;
+  } else {
+    double r = __builtin_amdgcn_rcp(k2);
+    r = __builtin_fma(r, __builtin_fma(-k2, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-k2, r, 1.0), r);
+    return (k2 == 0.0) ? 0.0 : green * r;
   }
 }
 

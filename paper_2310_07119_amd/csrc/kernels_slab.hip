@@ -202,8 +202,7 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
       const double k2o = k2z + k2x[q0 + PSTEP * j];
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const double k2 = k2o + k2y[t + TPP * m];
-        v[j][m] = mul_d(v[j][m], (k2 == 0.0) ? 0.0 : a.green / k2);
+        v[j][m] = mul_d(v[j][m], green_factor<T>(k2o + k2y[t + TPP * m], a.green));
       }
     }
     fft_all(v, true);
@@ -233,17 +232,13 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
     Regs v;
     load_rows(field_ptr<T>(a, fA), v);
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
-#pragma unroll
-      for (int m = 0; m < R; ++m) v[j][m] = kick_rotate<T>(v[j][m], (kick * (double)zv[j][m].re));
+    for (int j = 0; j < PPT; ++j) kick_values<T, R>(v[j], zv[j], false, kick);
     drift_xy(v);
     store_rows(field_ptr<T>(a, fA), v);
     if (hasB) {
       load_rows(field_ptr<T>(a, fB), v);
 #pragma unroll
-      for (int j = 0; j < PPT; ++j)
-#pragma unroll
-        for (int m = 0; m < R; ++m) v[j][m] = kick_rotate<T>(v[j][m], (kick * (double)zv[j][m].im));
+      for (int j = 0; j < PPT; ++j) kick_values<T, R>(v[j], zv[j], true, kick);
       drift_xy(v);
       store_rows(field_ptr<T>(a, fB), v);
     }

@@ -66,7 +66,8 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
   const int64_t pl = (int64_t)grp * C + cl;
   const bool act_l = pl < npencils;
   const int64_t pll = act_l ? pl : 0;
-  const int64_t base_l = (pll % stride) + (pll / stride) * stride * N;
+  const uint32_t p32 = (uint32_t)pll, s32 = (uint32_t)stride;  // cell counts stay below 2^31
+  const int64_t base_l = (int64_t)((p32 % s32) + (p32 / s32) * s32 * (uint32_t)N);
   // compute role: wavefront w, lane -> pencil slot and thread-in-pencil
   const int w = tid >> 6, lane = tid & 63;
   const int t = lane % TPP;
@@ -99,10 +100,12 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
     for (int m = 0; m < R; ++m) dst[lds_pad(t + TPP * m)] = v[m];
   };
   // pencil index (global) held by slot q, for k-space coordinates
-  auto pencil_base = [&](int q) -> int64_t {
-    const int64_t p = (int64_t)grp * C + slot(q);
-    const int64_t pp = p < npencils ? p : 0;
-    return (pp % stride) + (pp / stride) * stride * N;
+  // (cell counts stay below 2^31: 32-bit arithmetic)
+  auto pencil_base = [&](int q) -> uint32_t {
+    const uint32_t p = grp * (uint32_t)C + (uint32_t)slot(q);
+    const uint32_t pp = p < (uint32_t)npencils ? p : 0u;
+    const uint32_t st = (uint32_t)stride;
+    return (pp % st) + (pp / st) * st * (uint32_t)N;
   };
 
   TwiddleCache<T, N> tc;
@@ -178,8 +181,8 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         fwd(q, v);
       }
       if constexpr (MODE == PASS_ZPOISSON) {
-        const int64_t b = pencil_base(q);
-        const int64_t co[3] = {b % a.n[0], (b / a.n[0]) % a.n[1], b / ((int64_t)a.n[0] * a.n[1])};
+        const uint32_t b = pencil_base(q), n0 = (uint32_t)a.n[0], n1 = (uint32_t)a.n[1];
+        const uint32_t co[3] = {b % n0, (b / n0) % n1, b / (n0 * n1)};
         double k2o = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
@@ -187,8 +190,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         const double* __restrict__ k2a = a.k2[a.axis];
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-          const double k2 = k2o + k2a[t + TPP * m];
-          v[m] = mul_d(v[m], (k2 == 0.0) ? 0.0 : a.green / k2);
+          v[m] = mul_d(v[m], green_factor<T>(k2o + k2a[t + TPP * m], a.green));
         }
         inv(q, v);
       }
@@ -210,8 +212,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
           const double* __restrict__ k2a = a.k2[a.axis];
 #pragma unroll
           for (int m = 0; m < R; ++m) {
-            const double k2 = k2a[t + TPP * m];
-            V[q][m] = mul_d(V[q][m], (k2 == 0.0) ? 0.0 : a.green / k2);
+            V[q][m] = mul_d(V[q][m], green_factor<T>(k2a[t + TPP * m], a.green));
           }
         }
       }
@@ -247,10 +248,7 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
         cx<T> v[R];
         pencil_get(q, v);
         if constexpr (MODE == PASS_KICK_DRIFT) {
-#pragma unroll
-          for (int m = 0; m < R; ++m) {
-            v[m] = kick_rotate<T>(v[m], (kick * (double)(k == 0 ? V[q][m].re : V[q][m].im)));
-          }
+          kick_values<T, R>(v, V[q], k == 1, kick);
           drift(q, v);
           pencil_put(q, v);
         } else {

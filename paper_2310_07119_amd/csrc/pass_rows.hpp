@@ -33,7 +33,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   // slower in the kick pass with it and keep the runtime stride.
   constexpr bool UNIT = ROWS && sizeof(T) == 8;
   const int64_t stride = UNIT ? 1 : a.stride;
-  const int64_t base = UNIT ? pp * N : (pp % stride) + (pp / stride) * stride * N;
+  // (cell counts stay below 2^31: 32-bit index arithmetic)
+  const uint32_t p32 = (uint32_t)pp, s32 = (uint32_t)stride;
+  const int64_t base = UNIT ? pp * N : (int64_t)((p32 % s32) + (p32 / s32) * s32 * (uint32_t)N);
   const int64_t pair = a.pair0 + by;
   const int64_t fA = 2 * pair, fB = 2 * pair + 1;
   const bool hasB = fB < a.nfield;
@@ -153,10 +155,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       fft_pencil<T, N, false, SW>(zv, lds, t, tc);
     }
     if constexpr (MODE == PASS_ZPOISSON) {
-      const int64_t x0 = base % a.n[0];
-      const int64_t y0 = (base / a.n[0]) % a.n[1];
-      const int64_t z0 = base / ((int64_t)a.n[0] * a.n[1]);
-      const int64_t co[3] = {x0, y0, z0};
+      // grid coordinates of the pencil's first cell (cell counts stay below 2^31)
+      const uint32_t b32 = (uint32_t)base, n0 = (uint32_t)a.n[0], n1 = (uint32_t)a.n[1];
+      const uint32_t co[3] = {b32 % n0, (b32 / n0) % n1, b32 / (n0 * n1)};
       double k2o = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
@@ -164,9 +165,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       const double* __restrict__ k2a = a.k2[a.axis];
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const double k2 = k2o + k2a[t + TPP * m];
-        const double g = (k2 == 0.0) ? 0.0 : a.green / k2;
-        zv[m] = mul_d(zv[m], g);
+        zv[m] = mul_d(zv[m], green_factor<T>(k2o + k2a[t + TPP * m], a.green));
       }
       fft_pencil<T, N, true, SW>(zv, lds, t, tc);
     }
@@ -182,17 +181,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
     }
     if (a.store_v) store(zp, zv);  // the potentials, for the test particles
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      va[m] = kick_rotate<T>(va[m], (kick * (double)zv[m].re));
-    }
+    kick_values<T, R>(va, zv, false, kick);
     drift(va);
     store_psi(fA, va);
     if (hasB) {
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        vb[m] = kick_rotate<T>(vb[m], (kick * (double)zv[m].im));
-      }
+      kick_values<T, R>(vb, zv, true, kick);
       drift(vb);
       store_psi(fB, vb);
     }
@@ -216,8 +209,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
       const double* __restrict__ k2a = a.k2[a.axis];
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const double k2 = k2a[t + TPP * m];
-        zv[m] = mul_d(zv[m], (k2 == 0.0) ? 0.0 : a.green / k2);
+        zv[m] = mul_d(zv[m], green_factor<T>(k2a[t + TPP * m], a.green));
       }
     }
     fft_pencil<T, N, true, SW>(zv, lds, t, tc);
