@@ -64,7 +64,9 @@ def _rows(d):
     out = []
     for fn in files:
         with open(fn) as f:
-            out.extend(csv.DictReader(f))
+            for r in csv.DictReader(f):
+                r["_run"] = d  # dispatch ids repeat across runs: keys are (run, dispatch)
+                out.append(r)
     return out
 
 
@@ -76,7 +78,7 @@ def _per_dispatch(rows, counter, match):
         name = r.get("Kernel_Name", "")
         if not match(name):
             continue
-        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        key = (r.get("_run"), r.get("Dispatch_Id") or r.get("Correlation_Id"))
         vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
     return list(vals.values())
 
@@ -166,14 +168,19 @@ def kernels(a):
                 if ln.startswith("{") and '"metric"' in ln:
                     d = json.loads(ln)
                     bench[(d["config"]["precision"], d["roofline"]["kernel"])] = d["roofline"]["avg_launch_ms"] * 1e3
-        lines += [f"## Timed region: pass kernels, last {a.timed_launches} launches of each kind", "",
+        skip = f", before the last {a.skip_last}" if a.skip_last else ""
+        lines += [f"## Timed region: pass kernels, last {a.timed_launches} launches of each kind{skip}", "",
+                  "(bench.py runs the K timed steps, then the same K steps once more, profiled, outside the",
+                  "timed region; --skip-last K selects the timed launches, which the HIP-event column measures.)", "",
                   "The 2D passes alternate the axis they transform every step, so a kind's launches split",
                   "between its row kernel (`..., true>`) and its strided kernel. Kinds launched fewer times",
                   "per run than this (moments, energies) include warmup launches.", "",
                   "| precision | kind | kernel | launches | avg us |", "|---|---|---|---:|---:|"]
         summary = []
         for (prec, kind), seq in sorted(kinds.items()):
-            sel = seq[-a.timed_launches:]
+            sel = seq[-(a.timed_launches + a.skip_last):len(seq) - a.skip_last]
+            if not sel:  # kinds launched only outside the timed steps (moments, energies)
+                continue
             names = {}
             for name, d in sel:
                 names.setdefault(name, []).append(d)
@@ -219,8 +226,9 @@ def counters(a):
     names = sorted({r["Kernel_Name"] for r in rows if _kind_of(r["Kernel_Name"])})
     names = [n for n in names if f"<{ctype}, {a.length}," in n]
     fp = "F64" if a.precision == "fp64" else "F32"
-    table = [f"| kernel | kind | dispatches | VALU busy | {fp} FLOP/s (TFLOP/s) | LDS active | LDS bank-conflict cycles | conflicts per LDS access |",
-             "|---|---|---:|---:|---:|---:|---:|---:|"]
+    table = [f"| kernel | kind | dispatches | VALU busy | {fp} FLOP/s (TFLOP/s) | LDS active | LDS bank-conflict cycles | "
+             "conflicts per LDS access | wave time waiting | wave time issuing |",
+             "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for n in names:
         mode = int(n.split(",")[2].split(">")[0].strip())
         vals = {}
@@ -236,6 +244,7 @@ def counters(a):
         valu = vals.get("SQ_ACTIVE_INST_VALU")
         lds = vals.get("SQ_LDS_IDX_ACTIVE")
         conf = vals.get("SQ_LDS_BANK_CONFLICT")
+        wait, issue, wcyc = vals.get("SQ_WAIT_ANY"), vals.get("SQ_ACTIVE_INST_ANY"), vals.get("SQ_WAVE_CYCLES")
         fl = None
         if all(f"SQ_INSTS_VALU_{op}_{fp}" in vals for op in ("ADD", "MUL", "FMA")):
             fl = 64 * (vals[f"SQ_INSTS_VALU_ADD_{fp}"] + vals[f"SQ_INSTS_VALU_MUL_{fp}"] + 2 * vals[f"SQ_INSTS_VALU_FMA_{fp}"])
@@ -248,11 +257,14 @@ def counters(a):
         table.append(f"| `{n[:52]}` | {(_kind_of(n) or (None, mode))[1]} | {int(len(_per_dispatch(rows, 'GRBM_GUI_ACTIVE', lambda k, n=n: k == n)))} | "
                      f"{f(valu / cyc if valu else None)} | {f(fl / dur_s / 1e12 if fl else None, False)} | "
                      f"{f(lds / cyc if lds else None)} | {f(conf / cyc if conf else None)} | "
-                     f"{f(conf / (lds - conf) if (lds and conf) else None, False)} |")
+                     f"{f(conf / (lds - conf) if (lds and conf) else None, False)} | "
+                     f"{f(wait / wcyc if (wait and wcyc) else None)} | {f(issue / wcyc if (issue and wcyc) else None)} |")
     lines += table
     peak = "FP64 vector peak 78.6" if fp == "F64" else "FP32 vector peak 157.3"
     lines += ["", f"FLOP/s: 64 lanes x (ADD_{fp} + MUL_{fp} + 2 FMA_{fp}) instructions over the dispatch's own "
-              f"duration (its end minus start timestamp in the counter run); {peak} TFLOP/s.", ""]
+              f"duration (its end minus start timestamp in the counter run); {peak} TFLOP/s. Wave time waiting "
+              "and issuing: SQ_WAIT_ANY and SQ_ACTIVE_INST_ANY over SQ_WAVE_CYCLES (the share of the waves' "
+              "lifetime spent waiting on any dependency, and issuing any instruction).", ""]
     raw = ["| kernel | " + " | ".join(c.replace("SQ_", "").replace("GRBM_", "") for c in a.raw) + " |",
            "|---|" + "---:|" * len(a.raw)]
     for n in names:
@@ -287,6 +299,7 @@ def main():
     k.add_argument("--title", default="")
     k.add_argument("--bench-log", dest="bench_log", default="")
     k.add_argument("--timed-launches", dest="timed_launches", type=int, default=0)
+    k.add_argument("--skip-last", dest="skip_last", type=int, default=0)
     k.add_argument("--top", type=int, default=25)
     q = sub.add_parser("counters")
     q.add_argument("--dirs", nargs="+", required=True)
@@ -297,9 +310,10 @@ def main():
     q.add_argument("--commands", default="")
     q.add_argument("--cus", type=int, default=256)
     q.add_argument("--xcds", type=int, default=8)
-    q.add_argument("--raw", nargs="*", default=["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS",
-                                                 "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS",
-                                                 "SQ_WAVES", "GRBM_GUI_ACTIVE"])
+    q.add_argument("--raw", nargs="*", default=["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_SALU",
+                                                 "SQ_ACTIVE_INST_LDS", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT",
+                                                 "SQ_WAIT_INST_LDS", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "SQ_WAVES",
+                                                 "GRBM_GUI_ACTIVE"])
     a = ap.parse_args()
     if a.cmd == "counters":
         counters(a)
