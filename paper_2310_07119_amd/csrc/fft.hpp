@@ -372,6 +372,58 @@ struct FftStage {
   }
 };
 
+// Two pencils transformed in lockstep (each in its own LDS buffer): one pair
+// of synchronisations per stage serves both, and the two butterflies of a
+// stage are independent work for the scheduler to interleave.
+template <class T, int N, int TPP, bool INV, bool SW, int S>
+struct FftStage2 {
+  using One = FftStage<T, N, TPP, INV, SW, S>;
+  static constexpr int R = One::R, NS = One::NS, RS = One::RS, NSB = One::NSB, NB = One::NB;
+
+  template <class TC>
+  static __device__ __forceinline__ void run(cx<T> (&a)[R], cx<T> (&b)[R], cx<T>* la, cx<T>* lb, int t,
+                                             const TC& tc) {
+    if constexpr (S > 0) {
+      fft_sync<SW>();
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int j = t + TPP * i;
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+          a[i + r * NB] = la[lds_pad(j + r * (N / RS))];
+          b[i + r * NB] = lb[lds_pad(j + r * (N / RS))];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if constexpr (NSB > 1) {
+#pragma unroll
+        for (int r = 1; r < RS; ++r) {
+          tc.template apply<S, INV>(a[i + r * NB], i, r);
+          tc.template apply<S, INV>(b[i + r * NB], i, r);
+        }
+      }
+      Butterfly<T, RS, INV>::run(a, i, NB);
+      Butterfly<T, RS, INV>::run(b, i, NB);
+    }
+    if constexpr (S < NS - 1) {
+      fft_sync<SW>();
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int j = t + TPP * i;
+        const int base = (j / NSB) * NSB * RS + (j % NSB);
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+          la[lds_pad(base + r * NSB)] = a[i + r * NB];
+          lb[lds_pad(base + r * NSB)] = b[i + r * NB];
+        }
+      }
+      FftStage2<T, N, TPP, INV, SW, S + 1>::run(a, b, la, lb, t, tc);
+    }
+  }
+};
+
 // Transform the pencil held in v (natural layout) in place. `lds` is this
 // pencil's private buffer of fft_lds_stride(N) elements. With SYNC_WAVE =
 // false every thread of the workgroup must make the same calls (the stage
@@ -381,6 +433,12 @@ template <class T, int N, bool INV, bool SYNC_WAVE, bool CACHED>
 __device__ __forceinline__ void fft_pencil(cx<T> (&v)[N / fft_threads(N)], cx<T>* lds, int t,
                                            const TwiddleCache<T, N, CACHED>& tc) {
   FftStage<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(v, lds, t, tc);
+}
+// The same for two pencils at once (buffers la and lb).
+template <class T, int N, bool INV, bool SYNC_WAVE, bool CACHED>
+__device__ __forceinline__ void fft_pencil2(cx<T> (&a)[N / fft_threads(N)], cx<T> (&b)[N / fft_threads(N)],
+                                            cx<T>* la, cx<T>* lb, int t, const TwiddleCache<T, N, CACHED>& tc) {
+  FftStage2<T, N, fft_threads(N), INV, SYNC_WAVE, 0>::run(a, b, la, lb, t, tc);
 }
 
 }  // namespace tw

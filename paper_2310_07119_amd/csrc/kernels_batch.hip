@@ -64,17 +64,19 @@ __global__ void __launch_bounds__(256) grouped_kernel(GroupArgs g) {
 }
 
 template <class T, int N, int KIND>
-constexpr size_t grouped_lds_bytes() {
-  if constexpr (KIND == 0) return pass_lds_bytes<T, N, true>();
-  else if constexpr (KIND == 1) return pass_lds_bytes<T, N, false>();
+constexpr size_t grouped_lds_bytes(bool drifts) {
+  if constexpr (KIND == 0)
+    return drifts ? pass_lds_bytes<T, N, true, PASS_DRIFT>() : pass_lds_bytes<T, N, true, PASS_ZFWD>();
+  else if constexpr (KIND == 1)
+    return drifts ? pass_lds_bytes<T, N, false, PASS_DRIFT>() : pass_lds_bytes<T, N, false, PASS_ZFWD>();
   else return ColsCfg<T, N>::LDS;
 }
 
 template <class T, int KIND>
-size_t grouped_lds_for(int n) {
+size_t grouped_lds_for(int n, bool drifts) {
   switch (n) {
 #define TW_CASE(L) \
-  case L: return grouped_lds_bytes<T, L, KIND>();
+  case L: return grouped_lds_bytes<T, L, KIND>(drifts);
     TW_BATCH_LENGTHS(TW_CASE)
 #undef TW_CASE
     default: return 0;
@@ -107,7 +109,7 @@ static hipError_t launch_grouped_tk(int mode, GroupArgs& g, hipStream_t s) {
     const PassArgs& a = g.a[c];
     const int n = a.n[a.axis];
     const int pc = grouped_pencils_for<T, KIND>(n);
-    const size_t l = grouped_lds_for<T, KIND>(n);
+    const size_t l = grouped_lds_for<T, KIND>(n, pass_mode_drifts(mode));
     if (pc <= 0 || l == 0) return hipErrorInvalidValue;
     if (l > lds) lds = l;
     const int64_t npencils = a.ncell / n;

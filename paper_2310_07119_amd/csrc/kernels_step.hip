@@ -28,28 +28,33 @@ __global__ void __launch_bounds__((pass_threads<T, N, ROWS>())) pass_kernel(Pass
 template <class T, int N, bool ROWS>
 static hipError_t launch_pass_tnr(int mode, const PassArgs& a, hipStream_t s, int ny) {
   constexpr int C = pencils_per_group<T, N, ROWS>();
-  constexpr size_t LDS = pass_lds_bytes<T, N, ROWS>();
   const int64_t npencils = a.ncell / N;
   dim3 grid((unsigned)((npencils + C - 1) / C), (unsigned)ny);
   dim3 block(pass_threads<T, N, ROWS>());
-  auto go = [&](auto kern) -> hipError_t {
+  auto go = [&](auto mode_c) -> hipError_t {
+    constexpr int M = decltype(mode_c)::value;
+    constexpr size_t LDS = pass_lds_bytes<T, N, ROWS, M>();
+    const void* kern = reinterpret_cast<const void*>(pass_kernel<T, N, M, ROWS>);
     if constexpr (LDS > 64 * 1024) {
-      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), LDS);
+      hipError_t e = ensure_dynamic_lds(kern, LDS);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, grid, block, LDS, s, a);
+    hipLaunchKernelGGL((pass_kernel<T, N, M, ROWS>), grid, block, LDS, s, a);
     return hipGetLastError();
   };
   switch (mode) {
-    case PASS_DRIFT: return go(pass_kernel<T, N, PASS_DRIFT, ROWS>);
-    case PASS_DRIFT_RHO: return go(pass_kernel<T, N, PASS_DRIFT_RHO, ROWS>);
-    case PASS_ZFWD: return go(pass_kernel<T, N, PASS_ZFWD, ROWS>);
-    case PASS_ZPOISSON: return go(pass_kernel<T, N, PASS_ZPOISSON, ROWS>);
-    case PASS_ZINV: return go(pass_kernel<T, N, PASS_ZINV, ROWS>);
-    case PASS_KICK_DRIFT: return go(pass_kernel<T, N, PASS_KICK_DRIFT, ROWS>);
-    case PASS_RHO: return go(pass_kernel<T, N, PASS_RHO, ROWS>);
-    case PASS_KIN_SUM: return go(pass_kernel<T, N, PASS_KIN_SUM, ROWS>);
-    case PASS_POT_SUM: return go(pass_kernel<T, N, PASS_POT_SUM, ROWS>);
+#define TW_MODE(M) \
+  case M: return go(std::integral_constant<int, M>{});
+    TW_MODE(PASS_DRIFT)
+    TW_MODE(PASS_DRIFT_RHO)
+    TW_MODE(PASS_ZFWD)
+    TW_MODE(PASS_ZPOISSON)
+    TW_MODE(PASS_ZINV)
+    TW_MODE(PASS_KICK_DRIFT)
+    TW_MODE(PASS_RHO)
+    TW_MODE(PASS_KIN_SUM)
+    TW_MODE(PASS_POT_SUM)
+#undef TW_MODE
     default: return hipErrorInvalidValue;
   }
 }

@@ -171,30 +171,52 @@ __device__ __forceinline__ void cols_body(const PassArgs& a, unsigned bx, unsign
     gload(zp, st);
     tile_put(st);
     lds_barrier();
+    auto green = [&](int q, cx<T> (&v)[R]) {
+      const uint32_t b = pencil_base(q), n0 = (uint32_t)a.n[0], n1 = (uint32_t)a.n[1];
+      const uint32_t co[3] = {b % n0, (b / n0) % n1, b / (n0 * n1)};
+      double k2o = 0.0;
 #pragma unroll
-    for (int q = 0; q < ROUNDS; ++q) {
-      cx<T> v[R];
-      pencil_get(q, v);
-      if constexpr (MODE == PASS_ZINV) {
-        inv(q, v);
-      } else {
-        fwd(q, v);
-      }
-      if constexpr (MODE == PASS_ZPOISSON) {
-        const uint32_t b = pencil_base(q), n0 = (uint32_t)a.n[0], n1 = (uint32_t)a.n[1];
-        const uint32_t co[3] = {b % n0, (b / n0) % n1, b / (n0 * n1)};
-        double k2o = 0.0;
+      for (int d = 0; d < 3; ++d)
+        if (d != a.axis) k2o += a.k2[d][co[d]];
+      const double* __restrict__ k2a = a.k2[a.axis];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (d != a.axis) k2o += a.k2[d][co[d]];
-        const double* __restrict__ k2a = a.k2[a.axis];
+      for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], green_factor<T>(k2o + k2a[t + TPP * m], a.green));
+    };
+    if constexpr (ROUNDS % 2 == 0) {
+      // a wavefront's pencils two at a time, transformed in lockstep (each
+      // in its own tile slot, so no LDS beyond the tile)
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-          v[m] = mul_d(v[m], green_factor<T>(k2o + k2a[t + TPP * m], a.green));
+      for (int q = 0; q < ROUNDS; q += 2) {
+        cx<T> v0[R], v1[R];
+        pencil_get(q, v0);
+        pencil_get(q + 1, v1);
+        cx<T>* l0 = tile + slot(q) * LS;
+        cx<T>* l1 = tile + slot(q + 1) * LS;
+        fft_pencil2<T, N, MODE == PASS_ZINV, true>(v0, v1, l0, l1, t, tc);
+        if constexpr (MODE == PASS_ZPOISSON) {
+          green(q, v0);
+          green(q + 1, v1);
+          fft_pencil2<T, N, true, true>(v0, v1, l0, l1, t, tc);
         }
-        inv(q, v);
+        pencil_put(q, v0);
+        pencil_put(q + 1, v1);
       }
-      pencil_put(q, v);
+    } else {
+#pragma unroll
+      for (int q = 0; q < ROUNDS; ++q) {
+        cx<T> v[R];
+        pencil_get(q, v);
+        if constexpr (MODE == PASS_ZINV) {
+          inv(q, v);
+        } else {
+          fwd(q, v);
+        }
+        if constexpr (MODE == PASS_ZPOISSON) {
+          green(q, v);
+          inv(q, v);
+        }
+        pencil_put(q, v);
+      }
     }
     lds_barrier();
     tile_store(zp);

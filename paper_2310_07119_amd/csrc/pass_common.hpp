@@ -47,9 +47,28 @@ template <class T, int N, bool ROWS>
 __host__ __device__ constexpr int pass_threads() {
   return pencils_per_group<T, N, ROWS>() * fft_threads(N);
 }
-template <class T, int N, bool ROWS>
+// The drifting passes transform the two fields of a pair in lockstep (two
+// LDS buffers per pencil) where both buffers of every pencil fit in 80 KB per
+// workgroup, so that two workgroups still share a CU; the other passes keep
+// one buffer per pencil. Measured on MI355X at 512^2: FP32 drift+rho pass -9%,
+// FP32 kick pass -2%, FP64 drift+rho pass -3.5%; the FP64 kick pass, already
+// at two wavefronts per SIMD, ran 2.3% slower and keeps one transform at a time.
+#ifndef TW_PASS_DUAL
+#define TW_PASS_DUAL 1
+#endif
+__host__ __device__ constexpr bool pass_mode_drifts(int mode) {
+  return mode == PASS_DRIFT || mode == PASS_DRIFT_RHO || mode == PASS_KICK_DRIFT;
+}
+template <class T, int N, bool ROWS, int MODE>
+__host__ __device__ constexpr bool pass_dual() {
+  return TW_PASS_DUAL && pass_mode_drifts(MODE) && !(sizeof(T) == 8 && MODE == PASS_KICK_DRIFT) &&
+         (long)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 4 * (long)sizeof(T) <= 80 * 1024;
+}
+template <class T, int N, bool ROWS, int MODE>
 __host__ __device__ constexpr size_t pass_lds_bytes() {
-  return (size_t)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 2 * sizeof(T) + 16 * sizeof(double);
+  return (size_t)pencils_per_group<T, N, ROWS>() * fft_lds_stride(N) * 2 * sizeof(T) *
+             (pass_dual<T, N, ROWS, MODE>() ? 2 : 1) +
+         16 * sizeof(double);
 }
 
 template <class T>

@@ -13,14 +13,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
   constexpr int R = N / TPP;
   constexpr int C = pencils_per_group<T, N, ROWS>();
   constexpr bool SW = ROWS;  // wavefront-local exchanges
+  constexpr bool DUAL = pass_dual<T, N, ROWS, MODE>();  // the pair's two fields transformed in lockstep
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds_all = reinterpret_cast<cx<T>*>(smem_raw);
-  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * fft_lds_stride(N) * sizeof(cx<T>));
+  double* red = reinterpret_cast<double*>(smem_raw + (size_t)C * fft_lds_stride(N) * sizeof(cx<T>) * (DUAL ? 2 : 1));
 
   const int tid = threadIdx.x;
   const int c = ROWS ? tid / TPP : tid % C;
   const int t = ROWS ? tid % TPP : tid / C;
   cx<T>* lds = lds_all + c * fft_lds_stride(N);
+  cx<T>* ldsB = lds_all + (DUAL ? C + c : c) * fft_lds_stride(N);  // second buffer of the pencil slot
   const int64_t npencils = a.ncell / N;
   const unsigned grp = xcd_group_remap(bx, nbx);
   const int64_t p = (int64_t)grp * C + c;
@@ -114,21 +116,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
     for (int m = 0; m < R; ++m) v[m] = mul_d(v[m], ph[t + TPP * m]);
     fft_pencil<T, N, true, SW>(v, lds, t, tc);
   };
+  // both fields of the pair (vb is zero when the pair has no second field)
+  auto drift2 = [&](cx<T> (&x)[R], cx<T> (&y)[R]) {
+    fft_pencil2<T, N, false, SW>(x, y, lds, ldsB, t, tc);
+    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(a.phase);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const cx<double> f = ph[t + TPP * m];
+      x[m] = mul_d(x[m], f);
+      y[m] = mul_d(y[m], f);
+    }
+    fft_pencil2<T, N, true, SW>(x, y, lds, ldsB, t, tc);
+  };
   auto density = [&](const cx<T> (&v)[R], int64_t f, double (&rho)[R]) {
     const double mean = a.rho_mean ? a.rho_mean[f] : 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) rho[m] = a.m_tot * (double)abs2(v[m]) - mean;
   };
 
-  if constexpr (MODE == PASS_DRIFT) {
-    drift(va);
-    store_psi(fA, va);
-    if (hasB) {
-      drift(vb);
-      store_psi(fB, vb);
-    }
-  } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
-    if constexpr (MODE == PASS_DRIFT_RHO) {
+  // drift both fields of the pair and store them
+  auto drift_store = [&]() {
+    if constexpr (DUAL) {
+      drift2(va, vb);
+      store_psi(fA, va);
+      if (hasB) store_psi(fB, vb);
+    } else {
       drift(va);
       store_psi(fA, va);
       if (hasB) {
@@ -136,6 +148,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
         store_psi(fB, vb);
       }
     }
+  };
+
+  if constexpr (MODE == PASS_DRIFT) {
+    drift_store();
+  } else if constexpr (MODE == PASS_DRIFT_RHO || MODE == PASS_RHO) {
+    if constexpr (MODE == PASS_DRIFT_RHO) drift_store();
     double ra[R], rb[R];
     density(va, fA, ra);
     if (hasB) {
@@ -181,13 +199,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned bx, unsign
     }
     if (a.store_v) store(zp, zv);  // the potentials, for the test particles
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
-    kick_values<T, R>(va, zv, false, kick);
-    drift(va);
-    store_psi(fA, va);
-    if (hasB) {
-      kick_values<T, R>(vb, zv, true, kick);
-      drift(vb);
-      store_psi(fB, vb);
+    if constexpr (DUAL) {
+      kick_values<T, R>(va, zv, false, kick);
+      if (hasB) kick_values<T, R>(vb, zv, true, kick);
+      drift_store();
+    } else {  // one field at a time: kicking both first holds more registers
+      kick_values<T, R>(va, zv, false, kick);
+      drift(va);
+      store_psi(fA, va);
+      if (hasB) {
+        kick_values<T, R>(vb, zv, true, kick);
+        drift(vb);
+        store_psi(fB, vb);
+      }
     }
   } else if constexpr (MODE == PASS_KIN_SUM) {
     const double* __restrict__ k2a = a.k2[a.axis];

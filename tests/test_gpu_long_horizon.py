@@ -93,7 +93,10 @@ def _fp32_against_fp64(name, seed):
 # (normwise over the whole output array; scalars relative), measured on
 # MI355X:
 #   2D (5000 steps): mean_psi 2.4e-5, mean_rho 2.4e-5, var_rho 2.6e-5, norm
-#     2.0e-7, energy 1.4e-7, Q_raw 1.4e-8, dev_rho_L1 2.3e-7, dev_psi_L2 1.0e-6,
+#     2.0e-7, energy 1.4e-7, Q_raw 1.4e-8, dev_rho_L1 2.3e-7 to 5.5e-7 (a
+#     near-cancelling difference of the ensemble mean and the classical field:
+#     it moved with the order in which the compiler fuses the FP32 operations
+#     of the transforms, the other moments did not), dev_psi_L2 1.0e-6,
 #     classical energy 1.3e-6;
 #   3D (2000 steps): mean_psi 7.7e-6, mean_rho 1.0e-5, var_rho 8.8e-5, norm
 #     1.7e-7, energy 8.0e-8, Q_raw 1.6e-9, dev_rho_L1 6.0e-6, dev_psi_L2 7.2e-6,
@@ -101,7 +104,7 @@ def _fp32_against_fp64(name, seed):
 # The bounds are about twice these, and never above the FP32 bar of 1e-4.
 FP32_FULL_RUN_BOUNDS = {
     "2d_n512_pair": {"mean_psi": 5e-5, "mean_rho": 5e-5, "var_rho": 5.5e-5, "norm": 4e-7, "energy": 3e-7,
-                     "Q_raw": 3e-8, "dev_rho_L1": 5e-7, "dev_psi_L2": 2e-6, "energy_classical": 2.5e-6},
+                     "Q_raw": 3e-8, "dev_rho_L1": 1.1e-6, "dev_psi_L2": 2e-6, "energy_classical": 2.5e-6},
     "3d_n128_grf": {"mean_psi": 1.6e-5, "mean_rho": 2e-5, "var_rho": 1e-4, "norm": 3.5e-7, "energy": 1.6e-7,
                     "Q_raw": 3.2e-9, "dev_rho_L1": 1.2e-5, "dev_psi_L2": 1.5e-5, "energy_classical": 1.5e-7},
 }
