@@ -112,18 +112,21 @@ __device__ __forceinline__ void sincos_series(float x, float& s, float& c) {
   c = 1.f + x2 * pc;
 }
 
+// exp(-i x) for |x| <= 2^-5 (FP64): typical kick phases are far below pi/4,
+// and the series through x^7 / x^8 already leave a remainder below
+// x^9/9! < 2^-64 |x|
+__device__ __forceinline__ cx<double> expmi_small(double x) {
+  const double x2 = x * x;
+  const double ps = ((-1.0 / 5040.0) * x2 + 1.0 / 120.0) * x2 - 1.0 / 6.0;
+  const double pc = (((1.0 / 40320.0) * x2 - 1.0 / 720.0) * x2 + 1.0 / 24.0) * x2 - 0.5;
+  return {1.0 + x2 * pc, -(x + x * x2 * ps)};
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> expmi(double arg) {
   T s, c;
   if constexpr (sizeof(T) == 8) {
-    if (fabs(arg) <= 0.03125) {
-      // typical kick phases are far below pi/4: for |x| <= 2^-5 the series
-      // through x^7 / x^8 already leave a remainder below x^9/9! < 2^-64 |x|
-      const double x = arg, x2 = x * x;
-      const double ps = ((-1.0 / 5040.0) * x2 + 1.0 / 120.0) * x2 - 1.0 / 6.0;
-      const double pc = (((1.0 / 40320.0) * x2 - 1.0 / 720.0) * x2 + 1.0 / 24.0) * x2 - 0.5;
-      return {1.0 + x2 * pc, -(x + x * x2 * ps)};
-    }
+    if (fabs(arg) <= 0.03125) return expmi_small(arg);
   }
   if (fabs(arg) <= 0.78539816339744830962) {  // small kick phases
     sincos_series((T)arg, s, c);
@@ -226,8 +229,22 @@ __device__ __forceinline__ cx<T> kick_rotate(cx<T> v, double arg) {
 template <class T, int R>
 __device__ __forceinline__ void kick_values(cx<T> (&v)[R], const cx<T> (&pot)[R], bool im, double kick) {
   if constexpr (sizeof(T) == 8) {
+    // one branch per field: the short series for all R when every phase is
+    // below 2^-5 (the same values kick_rotate gives them)
+    double x[R];
+    bool small = true;
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], kick * (im ? pot[m].im : pot[m].re));
+    for (int m = 0; m < R; ++m) {
+      x[m] = kick * (im ? pot[m].im : pot[m].re);
+      small = small && fabs(x[m]) <= 0.03125;
+    }
+    if (small) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = cmul(v[m], expmi_small(x[m]));
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = kick_rotate<T>(v[m], x[m]);
+    }
   } else {
     const float kh = (float)kick, kl = (float)(kick - (double)kh);
     float x[R];

@@ -10,7 +10,10 @@
 // (pointwise layers, the four truncated DFT stages, weight gradients) runs on
 // the BF16 matrix-core GEMM; the pointwise GEMMs add the bias and the
 // spectral branch and apply GELU (forward) or GELU' (backward) in their
-// epilogue, in FP32; mode mixing runs in FP32, reductions in FP64.
+// epilogue, in FP32; mode mixing runs in FP32, reductions in FP64. With one
+// or two output channels the last projection's three contractions (dot
+// products per position, their outer-product backward, weighted column sums)
+// are streaming kernels on the same BF16-rounded operands.
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -366,6 +369,11 @@ int tw_fno_forward(tw_fno f, const float* params, const float* x, int32_t batch,
   e1.out2 = F.h;
   e1.act = 1;
   FNO_HIP(gemm(s, P, c.proj, C, 1.f, vL, C, 1, params + L.q1_w, c.proj, 1, 0.f, F.z1, c.proj, 1, 1, 0, 0, 0, e1));
+  // one or two output channels: streaming dot products per position (a
+  // matrix-core tile would compute 32 columns to keep one or two)
+  if (c.c_out <= 2 && launch_proj_out(F.h, params + L.q2_w, params + L.q2_b, y, P, c.proj, c.c_out, s) == hipSuccess)
+    return TW_OK;
+  (void)hipGetLastError();
   Epi e2;
   e2.bias = params + L.q2_b;
   FNO_HIP(gemm(s, P, c.c_out, c.proj, 1.f, F.h, c.proj, 1, params + L.q2_w, c.c_out, 1, 0.f, y, c.c_out, 1, 1, 0, 0,
@@ -384,14 +392,23 @@ int tw_fno_backward(tw_fno f, const float* params, const float* x, int32_t batch
   const int64_t P = positions(F, batch), C = c.width, K2 = 2LL * c.modes_y, mx = c.modes_x;
   const int64_t PC = (int64_t)F.max_batch * c.H * c.W * C;
   const int64_t bstride = (int64_t)F.max_batch * K2 * mx * C;
-  // projection 2
-  FNO_HIP(weight_grad(F, s, P, c.proj, c.c_out, F.h, dy, grads + L.q2_w));
+  // projection 2 (one or two output channels: a weighted column sum and an
+  // outer product with GELU' instead of matrix-core tiles of width 1 or 2)
+  const bool one = c.c_out <= 2 && launch_colsum_weighted(F.h, dy, c.c_out, P, c.proj, grads + L.q2_w, F.parts,
+                                                          F.parts_len, F.parts2, s) == hipSuccess;
+  if (!one) {
+    (void)hipGetLastError();
+    FNO_HIP(weight_grad(F, s, P, c.proj, c.c_out, F.h, dy, grads + L.q2_w));
+  }
   FNO_HIP(launch_colsum(dy, P, c.c_out, grads + L.q2_b, 0, F.parts, F.parts_len, F.parts2, s));
-  Epi eg;  // dz = (dy q2_w^T) GELU'(z1)
-  eg.gz = F.z1;
-  eg.gz_into_c = 1;
-  FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1, 1, 0, 0,
-               0, eg));
+  if (!one || launch_proj_out_back(dy, params + L.q2_w, F.z1, F.dz, P, c.proj, c.c_out, s) != hipSuccess) {
+    (void)hipGetLastError();
+    Epi eg;  // dz = (dy q2_w^T) GELU'(z1)
+    eg.gz = F.z1;
+    eg.gz_into_c = 1;
+    FNO_HIP(gemm(s, P, c.proj, c.c_out, 1.f, dy, c.c_out, 1, params + L.q2_w, 1, c.c_out, 0.f, F.dz, c.proj, 1, 1, 0,
+                 0, 0, eg));
+  }
   // projection 1
   const float* vL = F.v + (int64_t)c.layers * PC;
   FNO_HIP(weight_grad(F, s, P, C, c.proj, vL, F.dz, grads + L.q1_w));

@@ -33,6 +33,14 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 hipError_t launch_colsum(const float* x, int64_t P, int C, float* out, int accumulate, float* parts,
                          int64_t parts_len, double* tmp, hipStream_t st);
+// the output projection with one or two channels (forward, and backward to
+// the hidden layer with GELU'), and the weighted column sums of its weight gradient
+hipError_t launch_proj_out(const float* h, const float* w, const float* b, float* y, int64_t M, int K, int nout,
+                           hipStream_t st);
+hipError_t launch_proj_out_back(const float* dy, const float* w, const float* z, float* dz, int64_t M, int N,
+                                int nout, hipStream_t st);
+hipError_t launch_colsum_weighted(const float* x, const float* wt, int nw, int64_t P, int C, float* out, float* parts,
+                                  int64_t parts_len, double* tmp, hipStream_t st);
 hipError_t launch_sum_parts(const float* parts, int nparts, int64_t n, float* out, int accumulate, hipStream_t st,
                             double* tmp);  // tmp: [ceil(nparts/32)][n] FP64 sub-totals, or NULL
 hipError_t launch_modemix_fwd(const float* br, const float* bi, const float* Rr, const float* Ri, float* cr,
