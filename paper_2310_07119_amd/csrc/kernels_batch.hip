@@ -63,20 +63,27 @@ __global__ void __launch_bounds__(256) grouped_kernel(GroupArgs g) {
   }
 }
 
+// LDS of a pencil body per pass mode (the drifting modes may hold two
+// buffers per pencil; the FP64 kick pass and the transform-only modes one)
+template <class T, int N, bool ROWS>
+constexpr size_t pencil_lds_bytes(int mode) {
+  return mode == PASS_KICK_DRIFT     ? pass_lds_bytes<T, N, ROWS, PASS_KICK_DRIFT>()
+         : pass_mode_drifts(mode) ? pass_lds_bytes<T, N, ROWS, PASS_DRIFT>()
+                                  : pass_lds_bytes<T, N, ROWS, PASS_ZFWD>();
+}
+
 template <class T, int N, int KIND>
-constexpr size_t grouped_lds_bytes(bool drifts) {
-  if constexpr (KIND == 0)
-    return drifts ? pass_lds_bytes<T, N, true, PASS_DRIFT>() : pass_lds_bytes<T, N, true, PASS_ZFWD>();
-  else if constexpr (KIND == 1)
-    return drifts ? pass_lds_bytes<T, N, false, PASS_DRIFT>() : pass_lds_bytes<T, N, false, PASS_ZFWD>();
+constexpr size_t grouped_lds_bytes(int mode) {
+  if constexpr (KIND == 0) return pencil_lds_bytes<T, N, true>(mode);
+  else if constexpr (KIND == 1) return pencil_lds_bytes<T, N, false>(mode);
   else return ColsCfg<T, N>::LDS;
 }
 
 template <class T, int KIND>
-size_t grouped_lds_for(int n, bool drifts) {
+size_t grouped_lds_for(int n, int mode) {
   switch (n) {
 #define TW_CASE(L) \
-  case L: return grouped_lds_bytes<T, L, KIND>(drifts);
+  case L: return grouped_lds_bytes<T, L, KIND>(mode);
     TW_BATCH_LENGTHS(TW_CASE)
 #undef TW_CASE
     default: return 0;
@@ -109,7 +116,7 @@ static hipError_t launch_grouped_tk(int mode, GroupArgs& g, hipStream_t s) {
     const PassArgs& a = g.a[c];
     const int n = a.n[a.axis];
     const int pc = grouped_pencils_for<T, KIND>(n);
-    const size_t l = grouped_lds_for<T, KIND>(n, pass_mode_drifts(mode));
+    const size_t l = grouped_lds_for<T, KIND>(n, mode);
     if (pc <= 0 || l == 0) return hipErrorInvalidValue;
     if (l > lds) lds = l;
     const int64_t npencils = a.ncell / n;

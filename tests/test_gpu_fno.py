@@ -24,6 +24,9 @@ CFGS = {
     "tiny": dict(H=16, W=16, c_in=3, width=8, modes_x=4, modes_y=4, layers=2, proj=12, c_out=2),
     "ragged": dict(H=24, W=40, c_in=5, width=20, modes_x=6, modes_y=5, layers=3, proj=36, c_out=3),
     "workload": dict(H=256, W=256, c_in=4, width=32, modes_x=16, modes_y=16, layers=4, proj=128, c_out=2),
+    # one output channel and a 64-wide projection: the streaming projection
+    # kernels with one channel (the workload exercises two)
+    "one_out": dict(H=32, W=48, c_in=2, width=16, modes_x=6, modes_y=5, layers=2, proj=64, c_out=1),
 }
 
 
@@ -32,7 +35,7 @@ def _oracle_cfg(k):
                      layers=k["layers"], proj=k["proj"], c_out=k["c_out"])
 
 
-@pytest.mark.parametrize("name,batch", [("tiny", 2), ("ragged", 3), ("workload", 1)])
+@pytest.mark.parametrize("name,batch", [("tiny", 2), ("ragged", 3), ("workload", 1), ("one_out", 2)])
 def test_forward_backward_vs_oracle(name, batch):
     k = CFGS[name]
     net = Fno(**k, max_batch=batch, seed=3)
