@@ -38,7 +38,8 @@ struct SlabCfg {
   static constexpr int THREADS = threads_for(PENCIL_THREADS);
   static constexpr int PPT = PENCIL_THREADS / THREADS;           // pencils per thread
   static constexpr int PSTEP = THREADS / TPP;                    // pencil index step between them
-  static constexpr size_t LDS = (size_t)N * LS * sizeof(cx<T>) + 16 * sizeof(double);
+  // plane, reduction slots, and the drift factors along x and y (16 bytes each)
+  static constexpr size_t LDS = (size_t)N * LS * sizeof(cx<T>) + 16 * sizeof(double) + 2 * (size_t)N * 16;
   // 1024 threads leave 128 VGPRs per thread: twiddles are then read from the
   // table at each stage instead of being held in registers
   static constexpr bool TW_CACHED = THREADS < 1024;
@@ -61,6 +62,12 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);
   double* red = reinterpret_cast<double*>(smem_raw + (size_t)N * LS * sizeof(cx<T>));
+  // drift factors staged in LDS and read where they are applied: FP64 (cos,
+  // sin)/n, or for FP32 planes each factor as a pair of floats (f = hi + lo
+  // to 2^-48), applied with FP32 arithmetic. FP64 factors multiplied in FP64
+  // kept their conversions and products live across the transforms and made
+  // the 128-point FP32 planes spill.
+  unsigned char* phl = smem_raw + (size_t)N * LS * sizeof(cx<T>) + 16 * sizeof(double);
 
   const int tid = threadIdx.x;
   const int t = tid % TPP;
@@ -72,6 +79,20 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
 
   TwiddleCache<T, N, Cfg::TW_CACHED> tc;
   tc.load(reinterpret_cast<const cx<T>*>(a.twd), t);
+  if constexpr (MODE == SLAB_DRIFT || MODE == SLAB_DRIFT_RHO || MODE == SLAB_KICK_DRIFT) {
+    const cx<double>* p1 = reinterpret_cast<const cx<double>*>(a.phase);
+    const cx<double>* p2 = reinterpret_cast<const cx<double>*>(a.phase2);
+    for (int e = tid; e < 2 * N; e += Cfg::THREADS) {
+      const cx<double> f = e < N ? p1[e] : p2[e - N];
+      if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<cx<double>*>(phl)[e] = f;
+      } else {
+        const float hr = (float)f.re, hi = (float)f.im;
+        reinterpret_cast<float4*>(phl)[e] = make_float4(hr, hi, (float)(f.re - (double)hr), (float)(f.im - (double)hi));
+      }
+    }
+    slab_barrier();
+  }
 
   using Regs = cx<T>[PPT][R];
   auto load_rows = [&](const cx<T>* f, Regs& v) {
@@ -95,12 +116,27 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
       else fft_pencil<T, N, false, true, Cfg::TW_CACHED>(v[j], slot, t, tc);
     }
   };
-  auto phase_all = [&](Regs& v, const void* table) {
-    const cx<double>* __restrict__ ph = reinterpret_cast<const cx<double>*>(table);
+  auto phase_all = [&](Regs& v, int table) {
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
+    for (int m = 0; m < R; ++m) {
+      const int e = table * N + t + TPP * m;
+      if constexpr (sizeof(T) == 8) {
+        const cx<double> f = reinterpret_cast<const cx<double>*>(phl)[e];
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[j][m] = mul_d(v[j][m], ph[t + TPP * m]);
+        for (int j = 0; j < PPT; ++j) v[j][m] = mul_d(v[j][m], f);
+      } else {
+        const float4 f = reinterpret_cast<const float4*>(phl)[e];  // (hi.re, hi.im, lo.re, lo.im)
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          const cx<float> x = v[j][m];
+          const float cre = __builtin_fmaf(x.re, f.z, -x.im * f.w);
+          const float cim = __builtin_fmaf(x.re, f.w, x.im * f.z);
+          const float re = __builtin_fmaf(x.re, f.x, __builtin_fmaf(-x.im, f.y, cre));
+          const float im = __builtin_fmaf(x.re, f.y, __builtin_fmaf(x.im, f.x, cim));
+          v[j][m] = {re, im};
+        }
+      }
+    }
   };
   // rows in registers -> columns in registers (and back): through the plane layout
   auto rows_to_cols = [&](Regs& v) {
@@ -132,11 +168,11 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
   // drift along x (rows) then y (columns); rows in, rows out
   auto drift_xy = [&](Regs& v) {
     fft_all(v, false);
-    phase_all(v, a.phase);
+    phase_all(v, 0);
     fft_all(v, true);
     rows_to_cols(v);
     fft_all(v, false);
-    phase_all(v, a.phase2);
+    phase_all(v, 1);
     fft_all(v, true);
     cols_to_rows(v);
   };
@@ -227,7 +263,12 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
       mx = block_max(mx, red);
       if (tid == 0) record_max(a.vmax + ((plane + (unsigned)by) & (kVmaxBuckets - 1)), mx);
     }
-    if (a.store_v) store_rows(zp, zv);  // the potentials, for the test particles
+    // Planes of two pencils per thread park the potentials in the pair
+    // scratch during the first field's drift instead of holding them in
+    // registers (the 128-point FP32 kick pass spilled 112 registers), and read
+    // them back for the second field: 8 more bytes per pair and cell.
+    constexpr bool PARK = PPT > 1;
+    if (a.store_v || PARK) store_rows(zp, zv);  // the potentials (also for the test particles)
     const double kick = a.kick_dev ? a.kick_dev[0] : a.kick;
     Regs v;
     load_rows(field_ptr<T>(a, fA), v);
@@ -236,6 +277,7 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
     drift_xy(v);
     store_rows(field_ptr<T>(a, fA), v);
     if (hasB) {
+      if constexpr (PARK) load_rows(zp, zv);
       load_rows(field_ptr<T>(a, fB), v);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) kick_values<T, R>(v[j], zv[j], true, kick);
