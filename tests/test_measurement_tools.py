@@ -71,6 +71,50 @@ def test_counters_derived_figures(tmp_path):
     assert cells[8] == "0.50"
 
 
+def test_counters_from_several_runs_are_not_added(tmp_path):
+    # GRBM_GUI_ACTIVE in each of two counter runs with the same dispatch ids:
+    # each run's value is one dispatch's, so the VALU share stays 40%
+    g = 8 * 1000.0
+    _csv(tmp_path / "a", [(1, KICK, "GRBM_GUI_ACTIVE", g, 0, 1_000_000),
+                          (1, KICK, "SQ_ACTIVE_INST_VALU", 256 * 1000.0 * 0.4, 0, 1_000_000)])
+    _csv(tmp_path / "b", [(1, KICK, "GRBM_GUI_ACTIVE", g, 0, 1_000_000),
+                          (1, KICK, "SQ_WAIT_ANY", 250.0, 0, 1_000_000), (1, KICK, "SQ_WAVE_CYCLES", 1000.0, 0, 1_000_000),
+                          (1, KICK, "SQ_ACTIVE_INST_ANY", 300.0, 0, 1_000_000)])
+    out = tmp_path / "c.md"
+    a = types.SimpleNamespace(dirs=[str(tmp_path / "a"), str(tmp_path / "b")], out=str(out), precision="fp64",
+                              length=512, title="t", commands="c", cus=256, xcds=8, raw=["GRBM_GUI_ACTIVE"])
+    traffic.counters(a)
+    line = [l for l in open(out).read().splitlines() if l.startswith("| `void tw::pass_kernel<double, 512, 5")][0]
+    cells = [c.strip() for c in line.split("|")]
+    assert cells[4] == "40.0%"
+    assert cells[9] == "25.0%" and cells[10] == "30.0%"   # waiting and issuing shares of the wave time
+
+
+def test_kernel_summary_selects_the_timed_launches(tmp_path):
+    # a trace with 3 warmup, 2 timed and 2 re-profiled launches of the kick pass:
+    # --timed-launches 2 --skip-last 2 averages the timed ones
+    d = tmp_path / "kt"
+    os.makedirs(d)
+    with open(d / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"])
+        w.writeheader()
+        w.writerow(dict(Name=KICK, Calls=7, TotalDurationNs=1, AverageNs=1, Percentage=100, MinNs=1, MaxNs=1))
+    durs = [900, 900, 900, 500, 700, 100, 100]
+    with open(d / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        t = 0
+        for u in durs:
+            w.writerow(dict(Kernel_Name=KICK, Start_Timestamp=t, End_Timestamp=t + u * 1000))
+            t += 10_000_000
+    out = tmp_path / "k.md"
+    a = types.SimpleNamespace(dir=str(d), out=str(out), command="c", title="t", bench_log="", timed_launches=2,
+                              skip_last=2, top=5)
+    traffic.kernels(a)
+    rows = [l for l in open(out).read().splitlines() if l.startswith("| fp64 | pass_kick_drift | 2 |")]
+    assert rows and "600.0" in rows[0]
+
+
 def test_bench_algorithmic_bytes():
     sys.path.insert(0, ROOT)
     import bench
