@@ -6,7 +6,6 @@ hand-written backward must match central finite differences; BF16 rounding
 must be round-to-nearest-even; Adam must match its closed form on a quadratic.
 """
 import numpy as np
-import pytest
 
 from oracle import fno_oracle as fo
 
