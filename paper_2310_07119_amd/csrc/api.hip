@@ -187,6 +187,7 @@ hipError_t pass(Plan& P, PassArgs a, int mode, int axis, const void* phase, hipS
   a.twd = P.twd[axis];
   a.phase = phase;
   a.pair0 = pair0;
+  a.rev = (int32_t)(P.pass_seq++ & 1);
   if (npairs < 0) npairs = (a.nfield + 1) / 2 - pair0;
   return timed(P, mode, s, [&] { return launch_pass(P, mode, a, s, (int)npairs); });
 }
@@ -367,6 +368,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
         b.t_psi = t_psi;
         b.psi_t = buf[1 - cur][0];
         b.psi_cl_t = buf[1 - cur][1];
+        b.rev = (int32_t)(P.pass_seq++ & 1);
         hipError_t e = timed(P, mode, s, [&] { return launch_pass(P, mode, b, s, (int)nc); });
         if (t_psi) cur = 1 - cur;
         return e;
@@ -416,6 +418,7 @@ int enqueue_step(Plan& P, void* psi, void* psi_cl, int64_t nsteps, double dt, hi
         b.phase = phx;
         b.phase2 = phy;
         b.pair0 = c0;
+        b.rev = (int32_t)(P.pass_seq++ & 1);
         return timed(P, KIND_SLAB + mode, s, [&] { return launch_slab(P, mode, b, s, (int)nc); });
       };
       TW_HIP(zpass(PASS_DRIFT, ph_open(2)));

@@ -41,6 +41,7 @@ struct PassArgs {
   double* vmax;            // PASS_KICK_DRIFT / PASS_POT_SUM: running max |V|, kVmaxBuckets slots (atomic max on the bits)
   int32_t store_v;         // PASS_KICK_DRIFT: write the real-space potentials V_A + i V_B back into the pair scratch
   const void* phase2;      // plane passes (D = 3): drift factors along y (phase: along x)
+  int32_t rev;             // pair slots taken in reverse launch order (the last slot first)
 };
 
 // Passes over whole xy-planes of a D = 3 grid held in LDS (kernels_slab.hip).
@@ -101,6 +102,12 @@ struct Plan {
   int32_t slab_tuned;    // slab3d came from a measurement, the tuning cache or TW_SLAB
   int32_t cols_variant;  // kernel organisation of strided passes (autotuned, see tune.cpp)
   int32_t tuned;         // cols_variant came from a measurement or the tuning cache
+  // Passes enqueued on this plan so far. Consecutive passes walk the pairs in
+  // opposite orders, so that a pass starts on the pairs the previous one
+  // touched last, which are still in the 256 MB Infinity Cache (bit-identical
+  // results; measured on MI355X at 512^2 with 256 realizations: FP64 step
+  // -3.8%, FP32 -2.5%).
+  uint32_t pass_seq;
   // kernel timing (tw_plan_set_profiling)
   bool profiling;
   void* prof;            // opaque event record (api.hip)

@@ -9,7 +9,7 @@ namespace tw {
 
 template <class T, int N, int MODE>
 __global__ void __launch_bounds__((ColsCfg<T, N>::THREADS)) cols_kernel(PassArgs a) {
-  cols_body<T, N, MODE>(a, blockIdx.x, gridDim.x, blockIdx.y);
+  cols_body<T, N, MODE>(a, blockIdx.x, gridDim.x, pair_slot(a));
 }
 
 template <class T, int N>

@@ -289,7 +289,7 @@ __device__ __forceinline__ void slab_body(const PassArgs& a, unsigned plane, int
 
 template <class T, int N, int MODE>
 __global__ void __launch_bounds__((SlabCfg<T, N>::THREADS)) slab_kernel(PassArgs a) {
-  slab_body<T, N, MODE>(a, blockIdx.x, blockIdx.y);
+  slab_body<T, N, MODE>(a, blockIdx.x, pair_slot(a));
 }
 
 template <class T, int N>

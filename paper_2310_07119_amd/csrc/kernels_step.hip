@@ -22,7 +22,7 @@ namespace tw {
 
 template <class T, int N, int MODE, bool ROWS>
 __global__ void __launch_bounds__((pass_threads<T, N, ROWS>())) pass_kernel(PassArgs a) {
-  pass_body<T, N, MODE, ROWS>(a, blockIdx.x, gridDim.x, blockIdx.y);
+  pass_body<T, N, MODE, ROWS>(a, blockIdx.x, gridDim.x, pair_slot(a));
 }
 
 template <class T, int N, bool ROWS>

@@ -43,6 +43,10 @@ __device__ __forceinline__ unsigned xcd_group_remap(unsigned b, unsigned nb) {
   const unsigned k = b >> 3, x = b & 7;
   return (k / G) * (8 * G) + x * G + (k % G);
 }
+// Pair slot of this workgroup: grid rows in launch order, or reversed (a.rev).
+__device__ __forceinline__ unsigned pair_slot(const PassArgs& a) {
+  return a.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+}
 template <class T, int N, bool ROWS>
 __host__ __device__ constexpr int pass_threads() {
   return pencils_per_group<T, N, ROWS>() * fft_threads(N);

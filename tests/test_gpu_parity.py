@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from oracle import twa_oracle as tw
-from paper_2310_07119_amd import Problem, inputs
+from paper_2310_07119_amd import Plan, Problem, inputs
 from tests.gpu_util import TOL, gpu_run, oracle_problem, rel
 
 pytestmark = pytest.mark.gpu
@@ -197,3 +197,32 @@ def test_classical_limit_infinite_particle_number(precision):
     assert abs(m["Q_raw"]) < tol * np.mean(m["norm"])
     assert np.max(m["var_rho"]) < tol * np.max(m["mean_rho"]) ** 2
     assert m["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(64, 32), (16, 16, 32)], ids=["2d", "3d"])
+def test_pass_order_leaves_results_bit_identical(n, precision):
+    """Consecutive passes walk the pairs in alternating directions, continuing
+    from whatever the plan launched before. Every workgroup's arithmetic is
+    independent of that order, so a plan that has already run an odd number
+    of passes (one step of a scratch ensemble: five passes in the 2D and the
+    3D plane schedules, nine in the 3D pencil schedule) must give
+    bit-identical results to a fresh plan, whose passes all run the other way."""
+    dev = torch.device("cuda:0")
+    p = Problem(n=n, hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=1e5, n_real=5, precision=precision)
+    psi_cl = torch.from_numpy(inputs.lognormal_field(n, p.box, kcut=4, seed=3)).to(dev)
+    print(f"pass order {n} {precision}", flush=True)
+    fresh, used = Plan(p), Plan(p)
+    scratch = used.sample(psi_cl, 5)
+    used.step(scratch, 1, 2e-4)
+    out = []
+    for plan in (fresh, used):
+        psi = plan.sample(psi_cl, 11)
+        cl = psi_cl.to(p.cdtype).clone()
+        plan.step(psi, 7, 2e-4, cl)
+        torch.cuda.synchronize()
+        out.append((psi.cpu(), cl.cpu()))
+    fresh.close()
+    used.close()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
