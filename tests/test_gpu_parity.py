@@ -200,18 +200,20 @@ def test_classical_limit_infinite_particle_number(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [(64, 32), (16, 16, 32)], ids=["2d", "3d"])
-def test_pass_order_leaves_results_bit_identical(n, precision):
+@pytest.mark.parametrize("n,slab", [((64, 32), "0"), ((16, 16, 32), "0"), ((16, 16, 32), "1")],
+                         ids=["2d", "3d-pencils", "3d-planes"])
+def test_pass_order_leaves_results_bit_identical(n, slab, precision, monkeypatch):
     """Consecutive passes walk the pairs in alternating directions, continuing
     from whatever the plan launched before. Every workgroup's arithmetic is
     independent of that order, so a plan that has already run an odd number
     of passes (one step of a scratch ensemble: five passes in the 2D and the
     3D plane schedules, nine in the 3D pencil schedule) must give
     bit-identical results to a fresh plan, whose passes all run the other way."""
+    monkeypatch.setenv("TW_SLAB", slab)
     dev = torch.device("cuda:0")
     p = Problem(n=n, hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=1e5, n_real=5, precision=precision)
     psi_cl = torch.from_numpy(inputs.lognormal_field(n, p.box, kcut=4, seed=3)).to(dev)
-    print(f"pass order {n} {precision}", flush=True)
+    print(f"pass order {n} slab={slab} {precision}", flush=True)
     fresh, used = Plan(p), Plan(p)
     scratch = used.sample(psi_cl, 5)
     used.step(scratch, 1, 2e-4)
