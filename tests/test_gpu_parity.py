@@ -228,3 +228,33 @@ def test_pass_order_leaves_results_bit_identical(n, slab, precision, monkeypatch
     used.close()
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(64, 32), (16, 16, 32)], ids=["2d", "3d"])
+@pytest.mark.parametrize("env", [{"TW_CHUNK_PAIRS": "1"}, {"TW_STREAMS": "2"},
+                                 {"TW_CHUNK_PAIRS": "2", "TW_STREAMS": "2"}],
+                         ids=["chunks", "two_streams", "both"])
+def test_pair_chunks_and_streams_leave_results_bit_identical(env, n, precision, monkeypatch):
+    """Realizations are independent, so advancing the pairs in chunks through
+    all steps (TW_CHUNK_PAIRS) or splitting them over two streams (TW_STREAMS)
+    changes only the order of the work: the results must equal the default
+    schedule's bit for bit."""
+    dev = torch.device("cuda:0")
+    p = Problem(n=n, hbar_m=1.0, G=1.0, m_tot=20.0, n_tot=1e5, n_real=5, precision=precision)
+    psi_cl = torch.from_numpy(inputs.lognormal_field(n, p.box, kcut=4, seed=4)).to(dev)
+    print(f"pair schedule {env} {n} {precision}", flush=True)
+    out = []
+    for use_env in (False, True):
+        if use_env:
+            for k, v in env.items():
+                monkeypatch.setenv(k, v)
+        plan = Plan(p)
+        psi = plan.sample(psi_cl, 21)
+        cl = psi_cl.to(p.cdtype).clone()
+        plan.step(psi, 6, 2e-4, cl)
+        torch.cuda.synchronize()
+        out.append((psi.cpu(), cl.cpu()))
+        plan.close()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
